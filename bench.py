@@ -1,0 +1,155 @@
+"""Throughput benchmark: spin-flip attempts/s of batched parallel tempering.
+
+Workload: 256 independent Chimera C8 instances (N = 512, 1472 couplers),
+J uniform in {+-1..+-7}, K = 32 temperatures (beta geometric 0.1..5.0) x
+R = 2 replica sets = 64 lanes per instance, an exchange pass after every 10th
+Metropolis sweep (the elementary Monte Carlo step of Sec. III.B).  One step =
+10^5 sweeps of the whole batch (Metropolis sweeps, exchange passes, running
+minima) in one persistent launch, continuing the same chains.
+
+Prints one JSON line (rank 0, N = 1 GPU) with the roofline of the sweep kernel
+(integer VALU issue bound) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+# MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz (4 SIMD16 per CU).
+PEAK_INT32_OPS = 256 * 64 * 2.4e9
+# Algorithmic VALU issue slots per spin-flip attempt of the minimal
+# formulation ("Roofline"): 1/8 Philox4x32-10 call
+# (10 rounds x (2 quarter-rate 32x32->64 products = 8 slots + 2 xor3) / 8),
+# local field 2 (two 4-way byte dot products), decision 5.
+A_SLOTS = 10 * (2 * 4 + 2) / 8 + 2 + 5
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--sweeps", type=int, default=None, help="sweeps per step (default 10^5)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--block-waves", type=int, default=0)
+    return p.parse_args()
+
+
+def cpu_baseline(cfg, insts, budget_s):
+    """The CPU oracle, as it stands, on the host's cores: one instance per
+    thread, a prefix of the sweeps, scaled to attempts/s."""
+    import oracle
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    lanes = cfg["K"] * cfg["R"]
+    n_sites = 8 * cfg["L"] ** 2
+    # calibrate: one instance, a few sweeps
+    d = insts[0]
+    st = oracle.pt_init(d["L"], None, d["J"], d["K"], d["R"], d["instance_id"], cfg["seed"])
+    t0 = time.perf_counter()
+    oracle.pt_run(d["L"], None, d["J"], d["K"], d["R"], d["beta"], d["instance_id"], cfg["seed"],
+                  cfg["swap_interval"], 5, st)
+    per_sweep = (time.perf_counter() - t0) / 5
+    sweeps = max(10, int(budget_s / per_sweep))
+    done = []
+
+    def work(i):
+        d = insts[i]
+        s = oracle.pt_init(d["L"], None, d["J"], d["K"], d["R"], d["instance_id"], cfg["seed"])
+        oracle.pt_run(d["L"], None, d["J"], d["K"], d["R"], d["beta"], d["instance_id"],
+                      cfg["seed"], cfg["swap_interval"], sweeps, s)
+        done.append(i)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(cores)]
+    t0 = time.perf_counter()
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    el = time.perf_counter() - t0
+    attempts = cores * sweeps * n_sites * lanes
+    return {"value": attempts / el, "unit": "spin-flip attempts/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{cores} C8 instances x {sweeps} sweeps (one per thread), "
+                      f"{el:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1605_03607_amd as hs
+    cfg = workloads.batch_c8()
+    sweeps = args.sweeps or cfg["sweeps"]
+    insts = workloads.make_batch(cfg)
+    n_inst = len(insts)
+    lanes = cfg["K"] * cfg["R"]
+    n_sites = 8 * cfg["L"] ** 2
+    attempts_per_step = n_inst * lanes * n_sites * sweeps
+
+    batch = hs.PTBatch(insts, cfg["seed"], swap_interval=cfg["swap_interval"],
+                       block_waves=args.block_waves)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        batch.sweep(sweeps)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        batch.sweep(sweeps)
+        ev[s][1].record(stream)
+        print(f"# step {s + 1}/{args.steps} enqueued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    mism = batch.measure()
+    ms_per_step = wall * 1e3 / args.steps
+    value = attempts_per_step * args.steps / wall
+    k_avg_s = float(np.mean(kernel_ms)) / 1e3
+    achieved = attempts_per_step * A_SLOTS / k_avg_s
+    out = {
+        "metric": "spin-flip attempts/s (C8 PT batch)",
+        "value": value,
+        "unit": "spin-flip attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "instances": n_inst, "L": cfg["L"], "N": n_sites,
+                   "couplers": 1472, "K": cfg["K"], "R": cfg["R"], "sweeps_per_step": sweeps,
+                   "swap_interval": cfg["swap_interval"], "alphabet": "+-1..+-7"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
+                     "unit": "Tops/s (int32 VALU issue slots)",
+                     "frac": achieved / PEAK_INT32_OPS, "traffic": None,
+                     "kernel_ms_avg": float(np.mean(kernel_ms)),
+                     "slots_per_attempt": A_SLOTS},
+        "energy_mismatches": mism,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, insts, args.cpu_seconds)
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * hardspin -- C ABI of the MI355X (gfx950) parallel-tempering engine for
+ * Ising spin glasses on Chimera graphs, the hot path of the hard-instance
+ * search of Marshall, Martin-Mayor and Hen, "Practical engineering of hard
+ * spin-glass instances" (arXiv:1605.03607).
+ *
+ * Conventions shared by every entry point
+ *   - Cost function: H = sum over Chimera couplers of J_ij s_i s_j, minimised,
+ *     no fields (Eq. 1, Sec. II).
+ *   - Chimera C_L (Appendix A, Fig. 8): L x L cells, each a K_{4,4}.  Site id
+ *     i = 8 (L r + c) + 4 u + k for cell (r, c), side u, index k.  Couplers:
+ *     (r,c,0,k)-(r,c,1,k') inside a cell, (r,c,0,k)-(r+1,c,0,k) and
+ *     (r,c,1,k)-(r,c+1,1,k) between cells.  Canonical coupler order:
+ *     ascending (min id, max id); the full C_L has 24 L^2 - 8 L couplers.
+ *   - A spin bit b = 1 means s = -1.  Spins are exchanged "word-major": one
+ *     uint64 per site, bit l = the spin bit of replica lane l.
+ *   - Lanes, slots: an instance runs K temperatures x R replica sets
+ *     (K R <= 64 lanes).  Lane r K + k starts at temperature slot (k, r);
+ *     exchanges move configurations between slots of the same replica set
+ *     (Sec. II: swaps between neighbouring temperatures satisfying detailed
+ *     balance).  perm[k R + r] is the lane currently at slot (k, r).
+ *   - Sweep t (0-based, per instance): a Metropolis pass over all live sites
+ *     of colour 0, then of colour 1 (colour (r + c + u) mod 2), in every lane
+ *     ("full-lattice Metropolis sweeps", Sec. III.B), followed by an
+ *     exchange pass (ascending pairs per replica set) when
+ *     (t + 1) mod swap_interval == 0.  Every random number is a Philox4x32-10
+ *     output keyed by (instance_id, seed) at a counter fixed by (sweep,
+ *     site pair, slot, use), so results do not depend on the launch shape.
+ *   - Memory: every device pointer is owned by the caller and must stay
+ *     valid until the stream has finished the work enqueued on it.  The
+ *     library itself allocates no device memory.
+ *   - Errors: every call returns HS_OK (0) or a negative HS_E* code and sets
+ *     a thread-local message (hs_last_error).  Asynchronous device faults are
+ *     reported as HS_EHIP by the next call that synchronises.
+ */
+#ifndef HARDSPIN_H
+#define HARDSPIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HS_OK 0
+#define HS_EINVAL (-1)        /* malformed argument */
+#define HS_ENOSPACE (-2)      /* caller buffer or workspace too small */
+#define HS_EUNSUPPORTED (-3)  /* size outside the engine's limits (L > 16, K R > 64, |J| > 7) */
+#define HS_EHIP (-4)          /* HIP runtime error */
+#define HS_EMISMATCH (-5)     /* incremental and recomputed energies differ */
+
+#define HS_MAX_L 16
+#define HS_MAX_LANES 64
+#define HS_MAX_ABS_J 7
+
+/* Flags of hs_pt_desc.flags */
+#define HS_INIT_FROM_BUFFER 1u   /* pt_init reads initial spins from buffers->spins */
+#define HS_STOP_ON_AGREEMENT 2u  /* stop an instance once all replica sets agree (see pt_sweep) */
+
+/* One problem instance and its temperature ladder.  Host memory; read during
+ * the call only.
+ *   L            Chimera side, 1..16 (N = 8 L^2 sites)
+ *   live         N bytes, 1 = working qubit, 0 = missing; NULL = all live
+ *   J            couplings over the full canonical coupler list (24 L^2 - 8 L
+ *                entries); couplers touching a missing site are ignored;
+ *                |J| <= 7
+ *   instance_id  first word of the Philox key of this instance
+ *   K, R         temperatures and replica sets, 1 <= K, 1 <= R, K R <= 64
+ *   beta         K inverse temperatures, 0 < beta_0 < beta_1 < ... */
+typedef struct hs_instance {
+    int32_t L;
+    const uint8_t *live;
+    const int8_t *J;
+    uint32_t instance_id;
+    int32_t K;
+    int32_t R;
+    const double *beta;
+} hs_instance;
+
+/* A batch of instances simulated together in one persistent launch. */
+typedef struct hs_pt_desc {
+    int32_t n_inst;
+    const hs_instance *inst; /* host array of n_inst */
+    uint32_t seed;           /* second word of every Philox key */
+    int32_t swap_interval;   /* exchange pass after every swap_interval-th sweep; 0 = none */
+    uint32_t flags;          /* HS_INIT_FROM_BUFFER | HS_STOP_ON_AGREEMENT */
+    int32_t block_waves;     /* wavefronts per instance (1..16); 0 = chosen by the tuner */
+} hs_pt_desc;
+
+/* Device buffers of a batch (caller-owned; offsets per instance n):
+ *   spins     uint64 [sum_n N_n]   instance n starts at word sum_{m<n} N_m
+ *   perm      uint8  [n_inst][64]  slot -> lane (first K R entries used)
+ *   energy    int32  [n_inst][64]  per-lane energy, maintained incrementally
+ *   emin      int32  [n_inst][64]  running minimum per replica set (first R)
+ *   thit      int64  [n_inst][64]  completed sweeps when emin was first reached
+ *   swap_acc  uint32 [n_inst][64]  accepted exchanges per pair (k, k+1), set r at k R + r
+ *   t         int64  [n_inst]      completed sweeps (the Philox sweep counter)
+ *   stopped   int32  [n_inst]      1 once HS_STOP_ON_AGREEMENT ended the run
+ *   workspace bytes from pt_workspace_bytes(); tables and descriptors */
+typedef struct hs_buffers {
+    uint64_t *spins;
+    uint8_t *perm;
+    int32_t *energy;
+    int32_t *emin;
+    int64_t *thit;
+    uint32_t *swap_acc;
+    int64_t *t;
+    int32_t *stopped;
+    void *workspace;
+    size_t workspace_bytes;
+} hs_buffers;
+
+typedef struct hs_pt hs_pt; /* opaque host handle */
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int hs_version(void);
+
+/* Message of the last error on this thread (never NULL). */
+const char *hs_last_error(void);
+
+/* Bytes of device workspace pt_init needs for this batch.  Host only.
+ * HS_EINVAL / HS_EUNSUPPORTED for a malformed batch. */
+int pt_workspace_bytes(const hs_pt_desc *d, size_t *bytes);
+
+/* Validates the batch, builds the per-instance coupling words and the
+ * Metropolis / exchange threshold tables on the host (floor(2^32 exp(-x)) in
+ * double precision), uploads them into b->workspace with async copies on
+ * `stream` (a hipStream_t; NULL = default stream) and enqueues the initial
+ * state: spins from Philox (bit 31 of word i mod 4 of
+ * Philox((instance_id, seed), (0, i div 4, (k << 8) | r, 2)) for the lane at
+ * slot (k, r)) or from b->spins (HS_INIT_FROM_BUFFER), perm = identity,
+ * energies from Eq. 1, emin/thit, zero counters.  *out receives a host handle
+ * that keeps copies of the descriptor and buffer pointers. */
+int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream);
+
+/* Enqueues n_sweeps sweeps of every instance in one persistent kernel launch
+ * (Metropolis sweeps, exchange passes, running minima; Sec. II and III.B).
+ * With HS_STOP_ON_AGREEMENT an instance stops after the first sweep at which
+ * all its replica sets have the same running minimum and its completed sweep
+ * count is at least twice the largest first-hit count (ground state confirmed
+ * by agreement, Appendix B).  Asynchronous. */
+int pt_sweep(hs_pt *h, int64_t n_sweeps);
+
+/* Enqueues one extra exchange pass now, outside the sweep schedule, drawing
+ * from its own Philox use (counter word 3 = 3) so it never repeats the draws
+ * of the scheduled passes.  Asynchronous. */
+int pt_swap(hs_pt *h);
+
+/* Recomputes every lane energy from the spins (Eq. 1) into recomputed
+ * (device int32 [n_inst][64], caller-owned) and compares it with the
+ * incremental energies.  Synchronises the stream.  HS_EMISMATCH if any live
+ * lane differs; *n_mismatch (host, may be NULL) receives the count. */
+int pt_measure(hs_pt *h, int32_t *recomputed, int32_t *n_mismatch);
+
+/* Frees the host handle (device buffers stay the caller's). */
+int pt_destroy(hs_pt *h);
+
+/* One RAO move (Algorithm 1, Sec. II.A) as a pure host function.
+ * (w0, w1, w2, w3) = Philox((chain, seed), (step, proposal, 0, 4)); the
+ * coupler is the e-th live one in canonical order, e = floor(w0 E_live /
+ * 2^32); the new value is entry floor(w1 (n_alpha - 1) / 2^32) of the
+ * ascending alphabet with the current value removed (a sign flip for
+ * {-1, +1}).  `in` is not modified. */
+typedef struct hs_mutation {
+    int32_t edge;       /* index in the full canonical coupler list */
+    int8_t old_j;
+    int8_t new_j;
+    uint32_t w_accept;  /* uniform for hs_rao_accept */
+} hs_mutation;
+int instance_mutate(const hs_instance *in, const int8_t *alphabet, int n_alpha, uint32_t chain,
+                    uint32_t seed, uint32_t step, uint32_t proposal, hs_mutation *out);
+
+/* Algorithm 1's acceptance on ln TTS at search temperature t_s: returns 1 iff
+ * delta = ln_new - ln_cur >= 0 or w < floor(2^32 exp(delta / t_s)) (an
+ * infinite new value is accepted; inf - inf counts as 0), else 0. */
+int hs_rao_accept(double ln_cur, double ln_new, double t_s, uint32_t w);
+
+/* Hardness of candidate instances: n_restarts independent PT runs per
+ * candidate (restart rho keyed by (word 0 of Philox((instance_id, seed),
+ * (rho, 0, 0, 5)), seed)), each until replica agreement or s_max sweeps; all
+ * runs of all candidates share one persistent launch.  E_gs = min over
+ * restarts; TTS_rho = max(1, first-hit sweep of E_gs), +inf if restart rho
+ * never held E_gs; ln_tts = ln(lower median of TTS_rho) (+inf if censored).
+ * Sec. III.B (ground-state agreement cross-check) and Appendix B (stop after
+ * repeated agreement).  Requires R >= 2.  Blocks until done. */
+typedef struct hs_hardness_params {
+    int32_t n_restarts;
+    int32_t K;
+    int32_t R;
+    const double *beta;
+    int32_t swap_interval;
+    int64_t s_max;
+    uint32_t seed;
+    int32_t block_waves; /* 0 = tuner */
+} hs_hardness_params;
+
+typedef struct hs_tts_detail {
+    int32_t e_gs;
+    int32_t confirmed; /* E_gs reached by two restarts or two replica sets of one */
+    int32_t n_censored;
+    int64_t sweeps_total;
+} hs_tts_detail;
+
+/* Device scratch for hardness_eval: size from hardness_workspace_bytes(). */
+int hardness_workspace_bytes(const hs_instance *cands, int n, const hs_hardness_params *p,
+                             size_t *bytes);
+int hardness_eval(const hs_instance *cands, int n, const hs_hardness_params *p, void *scratch,
+                  size_t scratch_bytes, double *ln_tts_out, hs_tts_detail *detail, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HARDSPIN_H */

@@ -48,6 +48,9 @@ def lib():
         L.or_pt_run.argtypes = [C.c_int, C.c_void_p, _i8p, C.c_int, C.c_int, _f64p, C.c_uint32,
                                 C.c_uint32, C.c_int, C.c_int64, C.c_int, C.c_void_p, _u64p, _u8p,
                                 _i32p, _i32p, _i64p, _u32p, _i64p, _i32p]
+        L.or_pt_swap_extra.argtypes = [C.c_int, C.c_void_p, _i8p, C.c_int, C.c_int, _f64p,
+                                       C.c_uint32, C.c_uint32, _u64p, _u8p, _i32p, _u32p,
+                                       C.c_int64]
         L.or_lane_energies.argtypes = [C.c_int, C.c_void_p, _i8p, C.c_int, _u64p, _i32p]
         L.or_hardness_eval.argtypes = [C.c_int, C.c_void_p, _i8p, C.c_uint32, C.c_uint32, C.c_int,
                                        C.c_int, C.c_int, _f64p, C.c_int, C.c_int64, _f64p, _i32p,
@@ -155,6 +158,16 @@ def pt_run(L, live, J, K, R, beta, key0, key1, swap_interval, n_sweeps, state,
                            n_sweeps, 1 if stop_on_agreement else 0, op, state.spins, state.perm,
                            state.energy, state.emin, state.thit, state.swap_acc, state.t,
                            state.stopped), "pt_run")
+    return state
+
+
+def pt_swap_extra(L, live, J, K, R, beta, key0, key1, state):
+    """One exchange pass outside the schedule (use 3, counter = completed sweeps)."""
+    keep, lp = _live_ptr(live)
+    _check(lib().or_pt_swap_extra(L, lp, np.ascontiguousarray(J, np.int8), K, R,
+                                  np.ascontiguousarray(beta, np.float64), key0, key1,
+                                  state.spins, state.perm, state.energy, state.swap_acc,
+                                  int(state.t[0])), "pt_swap_extra")
     return state
 
 

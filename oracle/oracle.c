@@ -52,6 +52,7 @@
 #define OR_D_METRO_HI 0u
 #define OR_D_SWAP 1u
 #define OR_D_INIT 2u
+#define OR_D_SWAP_EXTRA 3u
 #define OR_D_MUTATE 4u
 #define OR_D_RESTART 5u
 #define OR_D_METRO_LO 7u
@@ -394,7 +395,7 @@ static void metropolis_site(PT *p, int i, int k, int r, uint32_t t, int phase)
  * u < floor(2^32 exp(-(beta_{k+1} - beta_k) d)), u = word 0 of
  * Philox(key, (t, k, r, D_SWAP)).  This ratio is the detailed-balance
  * acceptance for exchanging the two copies (Sec. II). */
-static void swap_sweep(PT *p, uint32_t t, uint32_t *swap_acc)
+static void swap_sweep(PT *p, uint32_t t, uint32_t use, uint32_t *swap_acc)
 {
     for (int r = 0; r < p->R; ++r)
         for (int k = 0; k + 1 < p->K; ++k) {
@@ -404,7 +405,7 @@ static void swap_sweep(PT *p, uint32_t t, uint32_t *swap_acc)
             if (d <= 0) {
                 accept = 1;
             } else {
-                uint32_t u = philox_word(t, (uint32_t)k, (uint32_t)r, OR_D_SWAP, p->key0, p->key1, 0);
+                uint32_t u = philox_word(t, (uint32_t)k, (uint32_t)r, use, p->key0, p->key1, 0);
                 accept = (uint64_t)u < or_swap_threshold(p->beta[k], p->beta[k + 1], d);
             }
             if (accept) {
@@ -459,7 +460,7 @@ int or_pt_run(int L, const uint8_t *live, const int8_t *J, int K, int R,
                 for (int r = 0; r < R; ++r)
                     for (int k = 0; k < K; ++k) metropolis_site(&p, i, k, r, tt, phase);
             }
-        if (swap_interval > 0 && ((*t + 1) % swap_interval) == 0) swap_sweep(&p, tt, swap_acc);
+        if (swap_interval > 0 && ((*t + 1) % swap_interval) == 0) swap_sweep(&p, tt, OR_D_SWAP, swap_acc);
         *t += 1;
         /* running minimum per replica set, after the sweep (and exchanges) */
         for (int r = 0; r < R; ++r) {
@@ -488,6 +489,33 @@ int or_pt_run(int L, const uint8_t *live, const int8_t *J, int K, int R,
     for (int l = 0; l < OR_MAX_LANES; ++l) energy[l] = l < p.lanes ? (int32_t)p.E[l] : 0;
     free(order);
     free(p.b);
+    inst_free(g);
+    return 0;
+}
+
+/* One exchange pass outside the sweep schedule, with its own Philox use
+ * (counter word 3 = 3) and counter word 0 = the completed sweep count; the
+ * lane energies are unchanged, so are the running minima. */
+int or_pt_swap_extra(int L, const uint8_t *live, const int8_t *J, int K, int R,
+                     const double *beta, uint32_t key0, uint32_t key1, uint64_t *spins,
+                     uint8_t *perm, int32_t *energy, uint32_t *swap_acc, int64_t t)
+{
+    if (K < 1 || R < 1 || K * R > OR_MAX_LANES) return -1;
+    Inst *g = inst_new(L, live, J);
+    if (!g) return -1;
+    PT p;
+    p.g = g;
+    p.K = K;
+    p.R = R;
+    p.lanes = K * R;
+    p.beta = beta;
+    p.key0 = key0;
+    p.key1 = key1;
+    p.b = NULL;
+    p.perm = perm;
+    (void)spins;
+    for (int l = 0; l < OR_MAX_LANES; ++l) p.E[l] = l < p.lanes ? energy[l] : 0;
+    swap_sweep(&p, (uint32_t)t, OR_D_SWAP_EXTRA, swap_acc);
     inst_free(g);
     return 0;
 }

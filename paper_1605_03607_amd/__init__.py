@@ -1,0 +1,261 @@
+"""Python binding of libhardspin (argument marshalling only).
+
+Every step of the parallel-tempering path runs in the library's gfx950
+kernels; this module only converts numpy / torch arguments into the C ABI of
+include/hardspin.h.  PyTorch is used for device memory and streams.  The
+library must have been built (`python -m paper_1605_03607_amd.build` or
+__graft_entry__.build()); importing the binding fails loudly otherwise.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhardspin.so")
+
+HS_INIT_FROM_BUFFER = 1
+HS_STOP_ON_AGREEMENT = 2
+
+_ERRORS = {-1: "HS_EINVAL", -2: "HS_ENOSPACE", -3: "HS_EUNSUPPORTED", -4: "HS_EHIP",
+           -5: "HS_EMISMATCH"}
+
+
+class HardspinError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class hs_instance(C.Structure):
+    _fields_ = [("L", C.c_int32), ("live", C.c_void_p), ("J", C.c_void_p),
+                ("instance_id", C.c_uint32), ("K", C.c_int32), ("R", C.c_int32),
+                ("beta", C.c_void_p)]
+
+
+class hs_pt_desc(C.Structure):
+    _fields_ = [("n_inst", C.c_int32), ("inst", C.POINTER(hs_instance)), ("seed", C.c_uint32),
+                ("swap_interval", C.c_int32), ("flags", C.c_uint32), ("block_waves", C.c_int32)]
+
+
+class hs_buffers(C.Structure):
+    _fields_ = [("spins", C.c_void_p), ("perm", C.c_void_p), ("energy", C.c_void_p),
+                ("emin", C.c_void_p), ("thit", C.c_void_p), ("swap_acc", C.c_void_p),
+                ("t", C.c_void_p), ("stopped", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t)]
+
+
+class hs_mutation(C.Structure):
+    _fields_ = [("edge", C.c_int32), ("old_j", C.c_int8), ("new_j", C.c_int8),
+                ("w_accept", C.c_uint32)]
+
+
+class hs_hardness_params(C.Structure):
+    _fields_ = [("n_restarts", C.c_int32), ("K", C.c_int32), ("R", C.c_int32),
+                ("beta", C.c_void_p), ("swap_interval", C.c_int32), ("s_max", C.c_int64),
+                ("seed", C.c_uint32), ("block_waves", C.c_int32)]
+
+
+class hs_tts_detail(C.Structure):
+    _fields_ = [("e_gs", C.c_int32), ("confirmed", C.c_int32), ("n_censored", C.c_int32),
+                ("sweeps_total", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhardspin.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1605_03607_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        L.hs_version.restype = C.c_int
+        L.hs_last_error.restype = C.c_char_p
+        L.pt_workspace_bytes.argtypes = [C.POINTER(hs_pt_desc), C.POINTER(C.c_size_t)]
+        L.pt_init.argtypes = [C.POINTER(C.c_void_p), C.POINTER(hs_pt_desc), C.POINTER(hs_buffers),
+                              C.c_void_p]
+        L.pt_sweep.argtypes = [C.c_void_p, C.c_int64]
+        L.pt_swap.argtypes = [C.c_void_p]
+        L.pt_measure.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
+        L.pt_destroy.argtypes = [C.c_void_p]
+        L.instance_mutate.argtypes = [C.POINTER(hs_instance), C.c_void_p, C.c_int, C.c_uint32,
+                                      C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(hs_mutation)]
+        L.hs_rao_accept.argtypes = [C.c_double, C.c_double, C.c_double, C.c_uint32]
+        L.hardness_workspace_bytes.argtypes = [C.POINTER(hs_instance), C.c_int,
+                                               C.POINTER(hs_hardness_params),
+                                               C.POINTER(C.c_size_t)]
+        L.hardness_eval.argtypes = [C.POINTER(hs_instance), C.c_int, C.POINTER(hs_hardness_params),
+                                    C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(hs_tts_detail),
+                                    C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return ["hs_version", "hs_last_error", "pt_workspace_bytes", "pt_init", "pt_sweep", "pt_swap",
+            "pt_measure", "pt_destroy", "instance_mutate", "hs_rao_accept",
+            "hardness_workspace_bytes", "hardness_eval"]
+
+
+def _check(rc):
+    if rc != 0:
+        raise HardspinError(rc, lib().hs_last_error().decode())
+
+
+class _HostInstances:
+    """Keeps the numpy arrays behind an hs_instance[] alive."""
+
+    def __init__(self, insts):
+        self.keep = []
+        self.arr = (hs_instance * max(1, len(insts)))()
+        for n, d in enumerate(insts):
+            J = np.ascontiguousarray(d["J"], np.int8)
+            beta = np.ascontiguousarray(d["beta"], np.float64)
+            live = d.get("live")
+            live = None if live is None else np.ascontiguousarray(live, np.uint8)
+            self.keep += [J, beta, live]
+            x = self.arr[n]
+            x.L = int(d["L"])
+            x.J = J.ctypes.data
+            x.beta = beta.ctypes.data
+            x.live = None if live is None else live.ctypes.data
+            x.instance_id = int(d.get("instance_id", n))
+            x.K = int(d["K"])
+            x.R = int(d["R"])
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class PTBatch:
+    """A batch of PT instances in device memory (pt_init .. pt_destroy).
+
+    insts: list of dicts with L, J, live (or None), K, R, beta, instance_id.
+    """
+
+    def __init__(self, insts, seed, swap_interval=1, flags=0, block_waves=0, init_spins=None,
+                 device="cuda", stream=None):
+        torch = _torch()
+        self.torch = torch
+        self.insts = insts
+        self.n = len(insts)
+        self.Ns = [8 * int(d["L"]) ** 2 for d in insts]
+        self.offsets = np.concatenate([[0], np.cumsum(self.Ns)]).astype(np.int64)
+        self.hi = _HostInstances(insts)
+        self.desc = hs_pt_desc(self.n, C.cast(self.hi.arr, C.POINTER(hs_instance)), seed,
+                               swap_interval, flags, block_waves)
+        nb = C.c_size_t(0)
+        _check(lib().pt_workspace_bytes(C.byref(self.desc), C.byref(nb)))
+        dev = torch.device(device)
+        n = max(1, self.n)
+        total = max(1, int(self.offsets[-1]))
+        self.spins = torch.zeros(total, dtype=torch.int64, device=dev)
+        if init_spins is not None:
+            self.spins.copy_(torch.from_numpy(np.ascontiguousarray(init_spins).view(np.int64)))
+        self.perm = torch.zeros((n, 64), dtype=torch.uint8, device=dev)
+        self.energy = torch.zeros((n, 64), dtype=torch.int32, device=dev)
+        self.emin = torch.zeros((n, 64), dtype=torch.int32, device=dev)
+        self.thit = torch.zeros((n, 64), dtype=torch.int64, device=dev)
+        self.swap_acc = torch.zeros((n, 64), dtype=torch.int32, device=dev)
+        self.t = torch.zeros(n, dtype=torch.int64, device=dev)
+        self.stopped = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.workspace = torch.zeros(max(16, nb.value), dtype=torch.uint8, device=dev)
+        self.recomputed = torch.zeros((n, 64), dtype=torch.int32, device=dev)
+        self.bufs = hs_buffers(self.spins.data_ptr(), self.perm.data_ptr(), self.energy.data_ptr(),
+                               self.emin.data_ptr(), self.thit.data_ptr(), self.swap_acc.data_ptr(),
+                               self.t.data_ptr(), self.stopped.data_ptr(),
+                               self.workspace.data_ptr(), nb.value)
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().pt_init(C.byref(h), C.byref(self.desc), C.byref(self.bufs),
+                             _stream_ptr(stream)))
+        self.h = h
+
+    def sweep(self, n_sweeps):
+        _check(lib().pt_sweep(self.h, int(n_sweeps)))
+
+    def swap(self):
+        _check(lib().pt_swap(self.h))
+
+    def measure(self):
+        """Recomputes energies on the device; returns the mismatch count."""
+        mm = C.c_int32(0)
+        rc = lib().pt_measure(self.h, C.c_void_p(self.recomputed.data_ptr()), C.byref(mm))
+        if rc not in (0, -5):
+            _check(rc)
+        return int(mm.value)
+
+    def state(self, n):
+        """Host copy of instance n's state, in the oracle's PTState layout."""
+        self.torch.cuda.synchronize()
+        d = self.insts[n]
+        K, R = int(d["K"]), int(d["R"])
+        a, b = int(self.offsets[n]), int(self.offsets[n + 1])
+        return dict(
+            spins=self.spins[a:b].cpu().numpy().view(np.uint64).copy(),
+            perm=self.perm[n, :K * R].cpu().numpy().copy(),
+            energy=self.energy[n].cpu().numpy().copy(),
+            emin=self.emin[n, :R].cpu().numpy().copy(),
+            thit=self.thit[n, :R].cpu().numpy().copy(),
+            swap_acc=self.swap_acc[n, :max(1, (K - 1) * R)].cpu().numpy().view(np.uint32).copy()
+            if K > 1 else np.zeros(1, np.uint32),
+            t=int(self.t[n].item()),
+            stopped=int(self.stopped[n].item()),
+        )
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def instance_mutate(inst, alphabet, chain, seed, step, proposal):
+    hi = _HostInstances([dict(inst, K=inst.get("K", 1), R=inst.get("R", 1),
+                              beta=inst.get("beta", np.ones(1)))])
+    alpha = np.ascontiguousarray(alphabet, np.int8)
+    out = hs_mutation()
+    _check(lib().instance_mutate(C.byref(hi.arr[0]), alpha.ctypes.data, len(alpha), chain, seed,
+                                 step, proposal, C.byref(out)))
+    return int(out.edge), int(out.old_j), int(out.new_j), int(out.w_accept)
+
+
+def rao_accept(ln_cur, ln_new, t_s, w):
+    return bool(lib().hs_rao_accept(ln_cur, ln_new, t_s, w))
+
+
+def hardness_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed, block_waves=0,
+                  stream=None):
+    """ln TTS per candidate (dicts with L, J, live, instance_id) plus details."""
+    torch = _torch()
+    hi = _HostInstances([dict(c, K=K, R=R, beta=beta) for c in cands])
+    beta_arr = np.ascontiguousarray(beta, np.float64)
+    p = hs_hardness_params(n_restarts, K, R, beta_arr.ctypes.data, swap_interval, s_max, seed,
+                           block_waves)
+    nb = C.c_size_t(0)
+    _check(lib().hardness_workspace_bytes(hi.arr, len(cands), C.byref(p), C.byref(nb)))
+    scratch = torch.zeros(max(16, nb.value), dtype=torch.uint8, device="cuda")
+    ln = np.zeros(len(cands), np.float64)
+    det = (hs_tts_detail * max(1, len(cands)))()
+    _check(lib().hardness_eval(hi.arr, len(cands), C.byref(p), C.c_void_p(scratch.data_ptr()),
+                               nb.value, ln.ctypes.data, det, _stream_ptr(stream)))
+    details = [dict(e_gs=det[i].e_gs, confirmed=bool(det[i].confirmed),
+                    n_censored=det[i].n_censored, sweeps_total=det[i].sweeps_total)
+               for i in range(len(cands))]
+    return ln, details

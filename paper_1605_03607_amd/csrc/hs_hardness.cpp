@@ -1,0 +1,189 @@
+// hardness_eval: time-to-solution of candidate instances from independent PT
+// restarts that stop on ground-state agreement (Sec. III.B cross-check of PT
+// ground-state energies; Appendix B agreement rule), all restarts of all
+// candidates in one persistent launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "hs_internal.h"
+
+using namespace hs;
+
+namespace {
+
+struct HardnessLayout {
+    size_t spins, perm, energy, emin, thit, sacc, t, stopped, ws, total, ws_bytes;
+};
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int build_batch(const hs_instance *cands, int n, const hs_hardness_params *p,
+                std::vector<hs_instance> &runs, hs_pt_desc &d)
+{
+    if (cands == nullptr || p == nullptr || n < 0) return fail(HS_EINVAL, "hardness: bad arguments");
+    if (p->n_restarts < 1 || p->R < 2 || p->s_max < 0 || p->beta == nullptr)
+        return fail(HS_EINVAL, "hardness: need n_restarts >= 1, R >= 2, s_max >= 0, beta");
+    runs.clear();
+    for (int c = 0; c < n; ++c)
+        for (int rho = 0; rho < p->n_restarts; ++rho) {
+            hs_instance x = cands[c];
+            const uint32_t ctr[4] = {uint32_t(rho), 0u, 0u, kUseRestart};
+            const uint32_t key[2] = {cands[c].instance_id, p->seed};
+            uint32_t w[4];
+            philox_host(ctr, key, w);
+            x.instance_id = w[0];
+            x.K = p->K;
+            x.R = p->R;
+            x.beta = p->beta;
+            runs.push_back(x);
+        }
+    d.n_inst = int32_t(runs.size());
+    d.inst = runs.data();
+    d.seed = p->seed;
+    d.swap_interval = p->swap_interval;
+    d.flags = HS_STOP_ON_AGREEMENT;
+    d.block_waves = p->block_waves;
+    return HS_OK;
+}
+
+int layout(const std::vector<hs_instance> &runs, const hs_pt_desc &d, HardnessLayout &L)
+{
+    size_t sites = 0;
+    for (const auto &r : runs) sites += size_t(8) * r.L * r.L;
+    const size_t m = std::max<size_t>(1, runs.size());
+    size_t o = 0;
+    L.spins = o;
+    o = up256(o + sites * 8);
+    L.perm = o;
+    o = up256(o + m * 64);
+    L.energy = o;
+    o = up256(o + m * 64 * 4);
+    L.emin = o;
+    o = up256(o + m * 64 * 4);
+    L.thit = o;
+    o = up256(o + m * 64 * 8);
+    L.sacc = o;
+    o = up256(o + m * 64 * 4);
+    L.t = o;
+    o = up256(o + m * 8);
+    L.stopped = o;
+    o = up256(o + m * 4);
+    L.ws = o;
+    size_t wsb = 0;
+    if (!runs.empty()) {
+        int rc = pt_workspace_bytes(&d, &wsb);
+        if (rc) return rc;
+    }
+    L.ws_bytes = wsb;
+    L.total = up256(o + wsb);
+    return HS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hardness_workspace_bytes(const hs_instance *cands, int n, const hs_hardness_params *p, size_t *bytes)
+{
+    if (bytes == nullptr) return fail(HS_EINVAL, "hardness_workspace_bytes: NULL");
+    std::vector<hs_instance> runs;
+    hs_pt_desc d{};
+    int rc = build_batch(cands, n, p, runs, d);
+    if (rc) return rc;
+    HardnessLayout L{};
+    rc = layout(runs, d, L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return HS_OK;
+}
+
+int hardness_eval(const hs_instance *cands, int n, const hs_hardness_params *p, void *scratch,
+                  size_t scratch_bytes, double *ln_tts_out, hs_tts_detail *detail, void *stream)
+{
+    if (ln_tts_out == nullptr || (n > 0 && scratch == nullptr))
+        return fail(HS_EINVAL, "hardness_eval: NULL argument");
+    std::vector<hs_instance> runs;
+    hs_pt_desc d{};
+    int rc = build_batch(cands, n, p, runs, d);
+    if (rc) return rc;
+    if (n == 0) return HS_OK;
+    HardnessLayout L{};
+    rc = layout(runs, d, L);
+    if (rc) return rc;
+    if (scratch_bytes < L.total) return fail(HS_ENOSPACE, "hardness_eval: scratch too small");
+    char *base = reinterpret_cast<char *>(scratch);
+    hs_buffers b{};
+    b.spins = reinterpret_cast<uint64_t *>(base + L.spins);
+    b.perm = reinterpret_cast<uint8_t *>(base + L.perm);
+    b.energy = reinterpret_cast<int32_t *>(base + L.energy);
+    b.emin = reinterpret_cast<int32_t *>(base + L.emin);
+    b.thit = reinterpret_cast<int64_t *>(base + L.thit);
+    b.swap_acc = reinterpret_cast<uint32_t *>(base + L.sacc);
+    b.t = reinterpret_cast<int64_t *>(base + L.t);
+    b.stopped = reinterpret_cast<int32_t *>(base + L.stopped);
+    b.workspace = base + L.ws;
+    b.workspace_bytes = L.ws_bytes;
+    hs_pt *h = nullptr;
+    rc = pt_init(&h, &d, &b, stream);
+    if (rc) return rc;
+    rc = pt_sweep(h, p->s_max);
+    if (rc) {
+        pt_destroy(h);
+        return rc;
+    }
+    const size_t m = runs.size();
+    std::vector<int32_t> emin(m * 64);
+    std::vector<int64_t> thit(m * 64), t(m);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(emin.data(), b.emin, m * 64 * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(thit.data(), b.thit, m * 64 * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.data(), b.t, m * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    pt_destroy(h);
+    if (e != hipSuccess) return fail(HS_EHIP, std::string("hardness_eval: ") + hipGetErrorString(e));
+    const int nr = p->n_restarts, R = p->R;
+    for (int c = 0; c < n; ++c) {
+        int32_t gs = INT32_MAX;
+        for (int rho = 0; rho < nr; ++rho)
+            for (int r = 0; r < R; ++r) gs = std::min(gs, emin[(size_t(c) * nr + rho) * 64 + r]);
+        int hits = 0, double_hit = 0, censored = 0;
+        int64_t sweeps = 0;
+        std::vector<double> tts(nr);
+        for (int rho = 0; rho < nr; ++rho) {
+            const size_t run = size_t(c) * nr + rho;
+            sweeps += t[run];
+            int64_t best = -1;
+            int sets = 0;
+            for (int r = 0; r < R; ++r)
+                if (emin[run * 64 + r] == gs) {
+                    ++sets;
+                    const int64_t th = thit[run * 64 + r];
+                    if (best < 0 || th < best) best = th;
+                }
+            if (sets >= 2) double_hit = 1;
+            if (best >= 0) {
+                ++hits;
+                tts[rho] = double(std::max<int64_t>(best, 1));
+            } else {
+                ++censored;
+                tts[rho] = INFINITY;
+            }
+        }
+        std::sort(tts.begin(), tts.end());
+        const double med = tts[(nr - 1) / 2];
+        ln_tts_out[c] = std::isinf(med) ? INFINITY : std::log(med);
+        if (detail) {
+            detail[c].e_gs = gs;
+            detail[c].confirmed = (hits >= 2 || double_hit) ? 1 : 0;
+            detail[c].n_censored = censored;
+            detail[c].sweeps_total = sweeps;
+        }
+    }
+    return HS_OK;
+}
+
+}  // extern "C"

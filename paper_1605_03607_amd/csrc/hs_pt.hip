@@ -1,0 +1,1019 @@
+// gfx950 kernels and C ABI of the parallel-tempering engine (libhardspin).
+//
+// Layout on the device (one workgroup per instance, persistent work queue):
+//   * Spins live in LDS "lane-major": one thread = one replica lane, and the
+//     four spins of one side of one K_{4,4} cell are the four bytes of one
+//     dword (byte = +1 or -1, i.e. 0x01 / 0xFF).  S[cell][side][lane].
+//   * The local field of a site is two v_dot4_i32_i8: the four spins of the
+//     opposite side of the cell times four coupling bytes, plus the two
+//     inter-cell neighbours (v_perm'd into one dword) times two coupling
+//     bytes.  Coupling bytes are -4 J, so the product with the site's own spin
+//     is 4 m = 2 dE directly (m = -s h, dE = 2 m).
+//   * Randomness: Philox4x32-10, one call per (sweep, phase, cell pair, slot)
+//     gives eight 16-bit halves, the high halves of the eight 32-bit
+//     Metropolis uniforms of the pair's two updated cell sides.  The low
+//     halves come from a second Philox use and are computed only when a lane
+//     ties on the high half (probability 2^-16 per attempt).
+//   * Thresholds: fast table thi[k][m] = T >> 16 (0x10000 for m <= 0) in LDS;
+//     the exact table T = floor(2^32 exp(-2 beta m)) in global memory for ties.
+//   * Exchange passes run in wavefront 0: the acceptance of pair (k, k+1) for
+//     every possible carried configuration is evaluated lane-parallel, then
+//     the sequential ascending pass follows the carried index.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hs_internal.h"
+
+namespace hs {
+namespace dev {
+
+constexpr uint32_t M0 = 0xD2511F53u;
+constexpr uint32_t M1 = 0xCD9E8D57u;
+constexpr uint32_t W0 = 0x9E3779B9u;
+constexpr uint32_t W1 = 0xBB67AE85u;
+
+// a ^ b ^ k in one v_bitop3_b32 (truth table 0x96); k must be wave-uniform.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
+    return d;
+}
+
+__device__ __forceinline__ void mul_hilo(uint32_t a, uint32_t b, uint32_t &hi, uint32_t &lo)
+{
+    const uint64_t p = uint64_t(a) * uint64_t(b);
+    hi = uint32_t(p >> 32);
+    lo = uint32_t(p);
+}
+
+// Rounds r0..9 (0-based) of Philox4x32-10 on state x with base key (k0, k1).
+__device__ __forceinline__ void philox_rounds(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3,
+                                              uint32_t k0, uint32_t k1, int r0)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r < r0) continue;
+        uint32_t h0, l0, h1, l1;
+        mul_hilo(x0, M0, h0, l0);
+        mul_hilo(x2, M1, h1, l1);
+        const uint32_t n0 = xor3(h1, x1, k0 + uint32_t(r) * W0);
+        const uint32_t n2 = xor3(h0, x3, k1 + uint32_t(r) * W1);
+        x0 = n0;
+        x1 = l1;
+        x2 = n2;
+        x3 = l0;
+    }
+}
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1)
+{
+    philox_rounds(c0, c1, c2, c3, k0, k1, 0);
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// Parts of a Metropolis Philox call that do not depend on the cell pair.
+// Counter = (t, c1, slot, use).  Round 0 multiplies the uniform sweep word t
+// and the per-lane slot word; round 1 multiplies one uniform word.
+struct MetroUniform {
+    uint32_t y0u;  // xor into the lane's low slot product -> round-2 x0
+    uint32_t y1;   // round-2 x1 (uniform)
+    uint32_t y2u;  // xor into the per-call high product -> round-2 x2
+};
+
+__device__ __forceinline__ MetroUniform metro_uniform(uint32_t t, uint32_t use, uint32_t k0, uint32_t k1)
+{
+    uint32_t h0, l0;
+    mul_hilo(t, M0, h0, l0);
+    const uint32_t x2 = h0 ^ use ^ k1;
+    uint32_t qh, ql;
+    mul_hilo(x2, M1, qh, ql);
+    MetroUniform u;
+    u.y0u = qh ^ (k0 + W0);
+    u.y1 = ql;
+    u.y2u = l0 ^ (k1 + W1);
+    return u;
+}
+
+// Per-lane slot products: (hi, lo) of M1 * slot.
+struct MetroLane {
+    uint32_t a;  // hi(M1 slot) ^ k0  -> round-0 x0 before the xor with c1
+    uint32_t lo; // lo(M1 slot)       -> round-1 x1
+};
+
+__device__ __forceinline__ uint4 metro_call(const MetroLane &ml, const MetroUniform &mu, uint32_t c1,
+                                            uint32_t k0, uint32_t k1)
+{
+    const uint32_t x0 = ml.a ^ c1;
+    uint32_t qh, ql;
+    mul_hilo(x0, M0, qh, ql);
+    uint32_t y0 = ml.lo ^ mu.y0u, y1 = mu.y1, y2 = qh ^ mu.y2u, y3 = ql;
+    philox_rounds(y0, y1, y2, y3, k0, k1, 2);
+    return make_uint4(y0, y1, y2, y3);
+}
+
+__device__ __forceinline__ uint32_t half16(uint4 w, int q)
+{
+    const uint32_t word = (q >> 1) == 0 ? w.x : (q >> 1) == 1 ? w.y : (q >> 1) == 2 ? w.z : w.w;
+    return (q & 1) ? (word >> 16) : (word & 0xFFFFu);
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Dynamic LDS layout of the sweep kernel.
+struct LdsLayout {
+    uint32_t S, zero, thi, tshi, E, perm, slot, emin, thit, sacc, udraw, misc, total;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int K_max, int tshi_max)
+{
+    LdsLayout l;
+    uint32_t o = 0;
+    l.S = o;
+    o += uint32_t(ncell_max) * 2 * 64 * 4;
+    l.zero = o;
+    o += 64 * 4;
+    l.thi = o;
+    o += uint32_t(K_max) * kMRow * 4;
+    l.tshi = o;
+    o += ((uint32_t(tshi_max) * 2 + 15) / 16) * 16;
+    l.E = o;
+    o += 64 * 4;
+    l.perm = o;
+    o += 64 * 4;
+    l.slot = o;
+    o += 64 * 4;
+    l.emin = o;
+    o += 64 * 4;
+    l.thit = o;
+    o += 64 * 8;
+    l.sacc = o;
+    o += 64 * 4;
+    l.udraw = o;
+    o += 64 * 4;
+    l.misc = o;
+    o += 16 * 4;
+    l.total = o;
+    return l;
+}
+
+struct SweepArgs {
+    const InstDev *inst;
+    const TableDev *tabs;
+    const uint32_t *ws32;     // workspace viewed as uint32
+    const int32_t *order;     // instance processing order (descending cost)
+    uint32_t *queue;          // work-queue counter
+    uint64_t *spins;
+    uint8_t *perm;
+    int32_t *energy;
+    int32_t *emin;
+    int64_t *thit;
+    uint32_t *swap_acc;
+    int64_t *t;
+    int32_t *stopped;
+    int32_t n_inst;
+    int32_t swap_interval;
+    int64_t n_sweeps;
+    uint32_t flags;
+    int32_t ncell_max, K_max, tshi_max;
+    int32_t lds_ts_ok;        // 1 if every ladder's fast exchange table fits in LDS
+};
+
+// Exchange decision for one candidate (lane-parallel): d = E_x - E_y with x at
+// slot k, y at slot k+1, uniform u.  Exact: d <= 0 or u < floor(2^32 e^{-db d}).
+__device__ __forceinline__ bool swap_accept(int d, uint32_t u, int k, const TableDev &tb,
+                                            const uint32_t *ws32, const uint16_t *tshi_lds,
+                                            bool use_lds)
+{
+    if (d <= 0) return true;
+    const int32_t *row = reinterpret_cast<const int32_t *>(ws32 + tb.ts_row_off);
+    const int32_t *dhi = reinterpret_cast<const int32_t *>(ws32 + tb.ts_dhi_off);
+    const int32_t *dmx = reinterpret_cast<const int32_t *>(ws32 + tb.ts_dmax_off);
+    const int32_t *frow = reinterpret_cast<const int32_t *>(ws32 + tb.ts_full_row_off);
+    uint32_t th = 0;
+    if (d <= dhi[k]) {
+        const int at = row[k] + d - 1;
+        th = use_lds ? tshi_lds[at] : reinterpret_cast<const uint16_t *>(ws32 + tb.ts_hi_off)[at];
+    }
+    const uint32_t u16 = u >> 16;
+    if (u16 != th) return u16 < th;
+    const uint32_t tf = d <= dmx[k] ? ws32[tb.ts_full_off + frow[k] + d - 1] : 0u;
+    return u < tf;
+}
+
+// One exchange pass of the current instance, run by wavefront 0.
+__device__ void exchange_pass(uint32_t t, uint32_t use, int K, int R, uint32_t key0, uint32_t key1,
+                              const TableDev &tb, const uint32_t *ws32, char *lds, const LdsLayout &L,
+                              bool use_lds)
+{
+    const int lane = threadIdx.x & 63;
+    int32_t *E = reinterpret_cast<int32_t *>(lds + L.E);
+    int32_t *perm = reinterpret_cast<int32_t *>(lds + L.perm);
+    uint32_t *sacc = reinterpret_cast<uint32_t *>(lds + L.sacc);
+    const uint16_t *tshi = reinterpret_cast<const uint16_t *>(lds + L.tshi);
+    // draws for every (k, r): lane l = k R + r
+    uint32_t udraw = 0;
+    if (lane < (K - 1) * R) udraw = philox(t, uint32_t(lane / R), uint32_t(lane % R), use, key0, key1).x;
+    for (int r = 0; r < R; ++r) {
+        const int o = lane < K ? perm[lane * R + r] : 0;
+        const int Eo = lane < K ? E[o] : 0;
+        int newp = o;
+        int c = 0;
+        for (int k = 0; k + 1 < K; ++k) {
+            const uint32_t u = __shfl(udraw, k * R + r, 64);
+            const int Eb = __shfl(Eo, k + 1, 64);
+            bool ok = false;
+            if (lane <= k) ok = swap_accept(Eo - Eb, u, k, tb, ws32, tshi, use_lds);
+            const uint64_t mask = __ballot(ok);
+            const int onext = __shfl(o, k + 1, 64);
+            const int ocar = __shfl(o, c, 64);
+            if ((mask >> c) & 1ull) {
+                if (lane == k) newp = onext;
+                if (lane == 0) sacc[k * R + r] += 1u;
+            } else {
+                if (lane == k) newp = ocar;
+                c = k + 1;
+            }
+        }
+        const int olast = __shfl(o, c, 64);
+        if (lane == K - 1) newp = olast;
+        if (lane < K) perm[lane * R + r] = newp;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The persistent sweep kernel.
+__global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
+{
+    extern __shared__ __align__(16) char lds[];
+    const LdsLayout L = lds_layout(a.ncell_max, a.K_max, a.tshi_max);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = __builtin_amdgcn_readfirstlane(int(blockDim.x >> 6));
+    uint32_t *S = reinterpret_cast<uint32_t *>(lds + L.S);
+    uint32_t *thi = reinterpret_cast<uint32_t *>(lds + L.thi);
+    int32_t *E = reinterpret_cast<int32_t *>(lds + L.E);
+    int32_t *perm = reinterpret_cast<int32_t *>(lds + L.perm);
+    int32_t *slot = reinterpret_cast<int32_t *>(lds + L.slot);
+    int32_t *emin = reinterpret_cast<int32_t *>(lds + L.emin);
+    int64_t *thit = reinterpret_cast<int64_t *>(lds + L.thit);
+    uint32_t *sacc = reinterpret_cast<uint32_t *>(lds + L.sacc);
+    int32_t *misc = reinterpret_cast<int32_t *>(lds + L.misc);
+    uint16_t *tshi = reinterpret_cast<uint16_t *>(lds + L.tshi);
+
+    reinterpret_cast<uint32_t *>(lds + L.zero)[lane] = 0u;
+
+    for (;;) {
+        if (tid == 0) misc[0] = int32_t(atomicAdd(a.queue, 1u));
+        __syncthreads();
+        const int qi = __builtin_amdgcn_readfirstlane(misc[0]);
+        __syncthreads();
+        if (qi >= a.n_inst) break;
+        const int n = __builtin_amdgcn_readfirstlane(a.order[qi]);
+        const InstDev d = a.inst[n];
+        const TableDev tb = a.tabs[d.tab];
+        const int K = d.K, R = d.R, nlanes = d.nlanes, ncell = d.ncell, Lc = d.L;
+        const uint32_t key0 = d.key0, key1 = d.key1;
+        const uint32_t *jw = a.ws32 + d.jw_off;
+        const uint32_t *livew = a.ws32 + d.live_off;
+        const uint64_t *sp = a.spins + d.spin_off;
+
+        // ---- load state ----
+        for (int q = wave; q < ncell * 2; q += nwaves) {
+            const uint32_t lm = livew[q];
+            uint32_t w = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t word = sp[q * 4 + k];
+                const uint32_t bit = ((lm >> k) & 1u) ? uint32_t((word >> lane) & 1ull) : 0u;
+                w |= (bit ? 0xFFu : 0x01u) << (8 * k);
+            }
+            S[q * 64 + lane] = w;
+        }
+        for (int i = tid; i < K * kMRow; i += blockDim.x) thi[i] = a.ws32[tb.thi_off + i];
+        if (a.lds_ts_ok) {
+            const uint32_t *src = a.ws32 + tb.ts_hi_off;
+            uint32_t *dst = reinterpret_cast<uint32_t *>(tshi);
+            for (int i = tid; i < (tb.lds_ts_entries + 1) / 2; i += blockDim.x) dst[i] = src[i];
+        }
+        if (tid < 64) {
+            E[tid] = a.energy[n * 64 + tid];
+            perm[tid] = a.perm[n * 64 + tid];
+            emin[tid] = a.emin[n * 64 + tid];
+            thit[tid] = a.thit[n * 64 + tid];
+            sacc[tid] = a.swap_acc[n * 64 + tid];
+        }
+        if (tid == 0) misc[1] = a.stopped[n];
+        __syncthreads();
+        if (tid < K * R) {
+            const int kk = tid / R, rr = tid % R;
+            slot[perm[tid]] = kk | (rr << 8);
+        }
+        __syncthreads();
+
+        int64_t t = a.t[n];
+        const bool stop_mode = (a.flags & HS_STOP_ON_AGREEMENT) != 0;
+        bool stopped = __builtin_amdgcn_readfirstlane(misc[1]) != 0;
+        const int npairs = d.npairs;
+
+        for (int64_t s = 0; s < a.n_sweeps && !stopped; ++s) {
+            const uint32_t tt = uint32_t(t);
+            // per-lane slot state
+            const int sl = slot[lane];
+            const int kslot = min(sl & 0xFF, K - 1);
+            const uint32_t sword = (uint32_t(sl & 0xFF) << 8) | uint32_t(sl >> 8);
+            MetroLane ml;
+            {
+                uint32_t h, l;
+                mul_hilo(sword, M1, h, l);
+                ml.a = h ^ key0;
+                ml.lo = l;
+            }
+            const MetroUniform mu = metro_uniform(tt, kUseMetroHi, key0, key1);
+            const uint32_t thi_base = L.thi + uint32_t(kslot * kMRow + kMaxM) * 4u;
+            const uint32_t *tfull = a.ws32 + tb.tfull_off + kslot * kMRow + kMaxM;
+            int e4 = 0;
+
+            for (int p = 0; p < 2; ++p) {
+                for (int j = wave; j < npairs; j += nwaves) {
+                    const uint32_t c1 = (uint32_t(j) << 1) | uint32_t(p);
+                    const uint4 rw = metro_call(ml, mu, c1, key0, key1);
+                    const int e4_save = e4;
+                    uint32_t own_orig[2], own_new[2];
+                    int qflag = 0;
+                    const int ncq = (2 * j + 1 < ncell) ? 2 : 1;
+                    // fast pass: decide on the high 16 bits
+                    for (int h = 0; h < ncq; ++h) {
+                        const int cell = 2 * j + h;
+                        const int r = cell / Lc, c = cell - r * Lc;
+                        const int u = (r + c + p) & 1;
+                        const int q = cell * 2 + u;
+                        const int na = u == 0 ? (r > 0 ? cell - Lc : -1) : (c > 0 ? cell - 1 : -1);
+                        const int nb = u == 0 ? (r + 1 < Lc ? cell + Lc : -1) : (c + 1 < Lc ? cell + 1 : -1);
+                        const uint32_t own = S[q * 64 + lane];
+                        const uint32_t oth = S[(cell * 2 + 1 - u) * 64 + lane];
+                        const uint32_t A = na >= 0 ? S[(na * 2 + u) * 64 + lane] : 0u;
+                        const uint32_t B = nb >= 0 ? S[(nb * 2 + u) * 64 + lane] : 0u;
+                        const uint32_t x01 = __builtin_amdgcn_perm(B, A, 0x05040100u);
+                        const uint32_t x23 = __builtin_amdgcn_perm(B, A, 0x07060302u);
+                        const uint32_t *jq = jw + q * 8;
+                        const uint32_t lm = livew[q];
+                        uint32_t nw = own;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const uint32_t xv = k < 2 ? x01 : x23;
+                            const int h4 = __builtin_amdgcn_sdot4(int(oth), int(jq[k]),
+                                                                  __builtin_amdgcn_sdot4(int(xv), int(jq[4 + k]), 0, false),
+                                                                  false);
+                            const int sgn = int(int8_t(uint8_t(own >> (8 * k))));
+                            const int m4 = __mul24(sgn, h4);
+                            const uint32_t th = *reinterpret_cast<const uint32_t *>(lds + thi_base + m4);
+                            const uint32_t u16 = half16(rw, 4 * h + k);
+                            const bool live = (lm >> k) & 1u;
+                            const bool acc = live && (u16 <= th);
+                            qflag |= int(live && u16 == th);
+                            nw ^= acc ? (0xFEu << (8 * k)) : 0u;
+                            e4 += acc ? m4 : 0;
+                        }
+                        own_orig[h] = own;
+                        own_new[h] = nw;
+                    }
+                    if (__any(qflag)) {
+                        // exact pass for this pair: full 32-bit uniforms
+                        const MetroUniform mlo = metro_uniform(tt, kUseMetroLo, key0, key1);
+                        const uint4 rl = metro_call(ml, mlo, c1, key0, key1);
+                        e4 = e4_save;
+                        for (int h = 0; h < ncq; ++h) {
+                            const int cell = 2 * j + h;
+                            const int r = cell / Lc, c = cell - r * Lc;
+                            const int u = (r + c + p) & 1;
+                            const int q = cell * 2 + u;
+                            const int na = u == 0 ? (r > 0 ? cell - Lc : -1) : (c > 0 ? cell - 1 : -1);
+                            const int nb = u == 0 ? (r + 1 < Lc ? cell + Lc : -1) : (c + 1 < Lc ? cell + 1 : -1);
+                            const uint32_t own = own_orig[h];
+                            const uint32_t oth = S[(cell * 2 + 1 - u) * 64 + lane];
+                            const uint32_t A = na >= 0 ? S[(na * 2 + u) * 64 + lane] : 0u;
+                            const uint32_t B = nb >= 0 ? S[(nb * 2 + u) * 64 + lane] : 0u;
+                            const uint32_t x01 = __builtin_amdgcn_perm(B, A, 0x05040100u);
+                            const uint32_t x23 = __builtin_amdgcn_perm(B, A, 0x07060302u);
+                            const uint32_t *jq = jw + q * 8;
+                            const uint32_t lm = livew[q];
+                            uint32_t nw = own;
+                            for (int k = 0; k < 4; ++k) {
+                                const uint32_t xv = k < 2 ? x01 : x23;
+                                const int h4 = __builtin_amdgcn_sdot4(int(oth), int(jq[k]),
+                                                                      __builtin_amdgcn_sdot4(int(xv), int(jq[4 + k]), 0, false),
+                                                                      false);
+                                const int sgn = int(int8_t(uint8_t(own >> (8 * k))));
+                                const int m4 = __mul24(sgn, h4);
+                                const uint32_t uu = (half16(rw, 4 * h + k) << 16) | half16(rl, 4 * h + k);
+                                const bool live = (lm >> k) & 1u;
+                                const bool acc = live && (m4 <= 0 || uu < tfull[m4 >> 2]);
+                                nw ^= acc ? (0xFEu << (8 * k)) : 0u;
+                                e4 += acc ? m4 : 0;
+                            }
+                            own_new[h] = nw;
+                        }
+                    }
+                    for (int h = 0; h < ncq; ++h) {
+                        const int cell = 2 * j + h;
+                        const int r = cell / Lc, c = cell - r * Lc;
+                        const int u = (r + c + p) & 1;
+                        S[(cell * 2 + u) * 64 + lane] = own_new[h];
+                    }
+                }
+                __syncthreads();
+            }
+            // ---- energies, running minima, exchange, agreement ----
+            if (lane < nlanes) atomicAdd(&E[lane], e4 >> 1);
+            __syncthreads();
+            if (wave == 0) {
+                if (a.swap_interval > 0 && ((t + 1) % a.swap_interval) == 0)
+                    exchange_pass(tt, kUseSwap, K, R, key0, key1, tb, a.ws32, lds, L, a.lds_ts_ok != 0);
+                const int ev = lane < nlanes ? E[lane] : INT32_MAX;
+                int agree = 1;
+                int64_t tmax = 0;
+                int em0 = 0;
+                for (int r = 0; r < R; ++r) {
+                    const bool mine = lane >= r * K && lane < (r + 1) * K;
+                    const int mn = wave_min(mine ? ev : INT32_MAX);
+                    int em = emin[r];
+                    int64_t th = thit[r];
+                    if (mn < em) {
+                        em = mn;
+                        th = t + 1;
+                        if (lane == 0) {
+                            emin[r] = em;
+                            thit[r] = th;
+                        }
+                    }
+                    if (r == 0) em0 = em;
+                    if (em != em0) agree = 0;
+                    tmax = th > tmax ? th : tmax;
+                }
+                if (lane == 0) misc[1] = (stop_mode && agree && (t + 1) >= 2 * tmax) ? 1 : 0;
+            }
+            __syncthreads();
+            if (tid < K * R) {
+                const int kk = tid / R, rr = tid % R;
+                slot[perm[tid]] = kk | (rr << 8);
+            }
+            stopped = __builtin_amdgcn_readfirstlane(misc[1]) != 0;
+            t += 1;
+            __syncthreads();
+        }
+
+        // ---- store state ----
+        uint64_t *spw = a.spins + d.spin_off;
+        const uint64_t lane_mask = nlanes >= 64 ? ~0ull : ((1ull << nlanes) - 1ull);
+        for (int q = wave; q < ncell * 2; q += nwaves) {
+            const uint32_t w = S[q * 64 + lane];
+            const uint32_t lm = livew[q];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t bits = __ballot(((w >> (8 * k)) & 0xFFu) == 0xFFu) & lane_mask;
+                if (lane == k) spw[q * 4 + k] = ((lm >> k) & 1u) ? bits : 0ull;
+            }
+        }
+        if (tid < 64) {
+            a.energy[n * 64 + tid] = tid < nlanes ? E[tid] : 0;
+            a.perm[n * 64 + tid] = uint8_t(perm[tid]);
+            a.emin[n * 64 + tid] = emin[tid];
+            a.thit[n * 64 + tid] = thit[tid];
+            a.swap_acc[n * 64 + tid] = sacc[tid];
+        }
+        if (tid == 0) {
+            a.t[n] = t;
+            a.stopped[n] = stopped ? 1 : 0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset_queue(uint32_t *q) { *q = 0u; }
+
+// ---------------------------------------------------------------------------
+// Initial state: one workgroup (one wavefront) per instance.
+struct InitArgs {
+    const InstDev *inst;
+    const uint32_t *ws32;
+    uint64_t *spins;
+    uint8_t *perm;
+    int32_t *energy;
+    int32_t *emin;
+    int64_t *thit;
+    uint32_t *swap_acc;
+    int64_t *t;
+    int32_t *stopped;
+    int32_t from_buffer;
+};
+
+__device__ int lane_energy(const InstDev &d, const uint32_t *ws32, const uint64_t *sp, int lane)
+{
+    const uint32_t *ed = ws32 + d.edge_off;
+    int e = 0;
+    for (int x = 0; x < d.n_live_edges; ++x) {
+        const uint32_t w = ed[x];
+        const int i = int(w & 0xFFFu), j = int((w >> 12) & 0xFFFu);
+        const int J = int(int8_t(uint8_t(w >> 24)));
+        const int bi = int((sp[i] >> lane) & 1ull), bj = int((sp[j] >> lane) & 1ull);
+        e += (bi ^ bj) ? -J : J;
+    }
+    return e;
+}
+
+__global__ void __launch_bounds__(64) k_pt_init(InitArgs a)
+{
+    const int n = blockIdx.x;
+    const int lane = threadIdx.x;
+    const InstDev d = a.inst[n];
+    const uint32_t *livew = a.ws32 + d.live_off;
+    uint64_t *sp = a.spins + d.spin_off;
+    const int K = d.K, R = d.R, nlanes = d.nlanes;
+    const uint64_t lane_mask = nlanes >= 64 ? ~0ull : ((1ull << nlanes) - 1ull);
+    const int kk = lane % max(K, 1), rr = lane / max(K, 1);
+    for (int q = 0; q < d.ncell * 2; ++q) {
+        const uint32_t lm = livew[q];
+        uint4 w = make_uint4(0, 0, 0, 0);
+        if (!a.from_buffer && lane < nlanes)
+            w = philox(0u, uint32_t(q), (uint32_t(kk) << 8) | uint32_t(rr), kUseInit, d.key0, d.key1);
+        const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+        for (int k = 0; k < 4; ++k) {
+            uint64_t bits;
+            if (a.from_buffer)
+                bits = sp[q * 4 + k] & lane_mask;
+            else
+                bits = __ballot(lane < nlanes && (ww[k] >> 31) != 0u) & lane_mask;
+            if (!((lm >> k) & 1u)) bits = 0ull;
+            if (lane == 0) sp[q * 4 + k] = bits;
+        }
+    }
+    __syncthreads();
+    const int ev = lane < nlanes ? lane_energy(d, a.ws32, sp, lane) : 0;
+    a.energy[n * 64 + lane] = ev;
+    a.perm[n * 64 + lane] = lane < K * R ? uint8_t((lane % R) * K + lane / R) : uint8_t(0);
+    int em = 0;
+    for (int r = 0; r < R; ++r) {
+        const bool mine = lane >= r * K && lane < (r + 1) * K;
+        const int mn = wave_min(mine ? ev : INT32_MAX);
+        if (lane == r) em = mn;
+    }
+    a.emin[n * 64 + lane] = lane < R ? em : 0;
+    a.thit[n * 64 + lane] = 0;
+    a.swap_acc[n * 64 + lane] = 0u;
+    if (lane == 0) {
+        a.t[n] = 0;
+        a.stopped[n] = 0;
+    }
+}
+
+// Recomputed lane energies (Eq. 1) and count of mismatches.
+__global__ void __launch_bounds__(64) k_energy(const InstDev *inst, const uint32_t *ws32,
+                                               const uint64_t *spins, const int32_t *energy,
+                                               int32_t *out, int32_t *mismatch)
+{
+    const int n = blockIdx.x, lane = threadIdx.x;
+    const InstDev d = inst[n];
+    const int ev = lane < d.nlanes ? lane_energy(d, ws32, spins + d.spin_off, lane) : 0;
+    out[n * 64 + lane] = ev;
+    if (lane < d.nlanes && ev != energy[n * 64 + lane]) atomicAdd(mismatch, 1);
+}
+
+// One extra exchange pass per instance (pt_swap).
+__global__ void __launch_bounds__(64) k_swap_extra(const InstDev *inst, const TableDev *tabs,
+                                                   const uint32_t *ws32, uint8_t *perm_g,
+                                                   const int32_t *energy, uint32_t *swap_acc,
+                                                   const int64_t *t, int ncell_max, int K_max,
+                                                   int tshi_max)
+{
+    extern __shared__ __align__(16) char lds[];
+    const LdsLayout L = lds_layout(ncell_max, K_max, tshi_max);
+    const int n = blockIdx.x, lane = threadIdx.x;
+    const InstDev d = inst[n];
+    const TableDev tb = tabs[d.tab];
+    int32_t *E = reinterpret_cast<int32_t *>(lds + L.E);
+    int32_t *perm = reinterpret_cast<int32_t *>(lds + L.perm);
+    uint32_t *sacc = reinterpret_cast<uint32_t *>(lds + L.sacc);
+    E[lane] = energy[n * 64 + lane];
+    perm[lane] = perm_g[n * 64 + lane];
+    sacc[lane] = swap_acc[n * 64 + lane];
+    __syncthreads();
+    exchange_pass(uint32_t(t[n]), kUseSwapExtra, d.K, d.R, d.key0, d.key1, tb, ws32, lds, L, false);
+    __syncthreads();
+    perm_g[n * 64 + lane] = uint8_t(perm[lane]);
+    swap_acc[n * 64 + lane] = sacc[lane];
+}
+
+}  // namespace dev
+}  // namespace hs
+
+// ===========================================================================
+// Host side of the ABI.
+using namespace hs;
+
+struct hs_pt {
+    int n_inst = 0;
+    hs_buffers buf{};
+    hipStream_t stream = nullptr;
+    uint32_t flags = 0;
+    int32_t swap_interval = 0;
+    int nwaves = 16;
+    int grid = 0;
+    int ncell_max = 0, K_max = 0, tshi_max = 0;
+    int lds_ts_ok = 1;
+    size_t lds_bytes = 0;
+    // workspace layout (byte offsets)
+    size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0;
+    std::vector<uint32_t> host_ws;  // staging image of the workspace (kept until destroy)
+};
+
+namespace {
+
+constexpr size_t kLdsTsBudget = 48 * 1024;  // bytes of LDS for the 16-bit exchange table
+
+struct Plan {
+    std::vector<HostInstance> hi;
+    std::vector<HostTables> ht;
+    std::vector<int> tab_of;
+    std::vector<InstDev> idev;
+    std::vector<TableDev> tdev;
+    std::vector<int32_t> order;
+    std::vector<uint32_t> image;  // workspace image in uint32 words
+    size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0;
+    int ncell_max = 0, K_max = 0, tshi_max = 0;
+    int lds_ts_ok = 1;
+    size_t total_words = 0;
+};
+
+size_t align16w(size_t w) { return (w + 3) & ~size_t(3); }
+
+template <class T>
+size_t append(std::vector<uint32_t> &img, const T *p, size_t count)
+{
+    const size_t at = align16w(img.size());
+    img.resize(at);
+    const size_t words = (count * sizeof(T) + 3) / 4;
+    img.resize(at + words, 0u);
+    if (count) std::memcpy(img.data() + at, p, count * sizeof(T));
+    return at;
+}
+
+int validate_inst(const hs_instance &in, std::string &err)
+{
+    if (in.K < 1 || in.R < 1 || in.K * in.R > HS_MAX_LANES) {
+        err = "need K >= 1, R >= 1, K*R <= 64";
+        return HS_EUNSUPPORTED;
+    }
+    if (in.beta == nullptr) {
+        err = "beta is NULL";
+        return HS_EINVAL;
+    }
+    for (int k = 0; k < in.K; ++k) {
+        if (!(in.beta[k] > 0.0) || !std::isfinite(in.beta[k])) {
+            err = "beta must be positive and finite";
+            return HS_EINVAL;
+        }
+        if (k > 0 && !(in.beta[k] > in.beta[k - 1])) {
+            err = "beta must be strictly ascending";
+            return HS_EINVAL;
+        }
+    }
+    return HS_OK;
+}
+
+int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
+{
+    if (d.n_inst < 0 || (d.n_inst > 0 && d.inst == nullptr)) {
+        err = "bad instance array";
+        return HS_EINVAL;
+    }
+    if (d.swap_interval < 0) {
+        err = "swap_interval must be >= 0";
+        return HS_EINVAL;
+    }
+    if (d.block_waves < 0 || d.block_waves > 16) {
+        err = "block_waves must be in 0..16";
+        return HS_EINVAL;
+    }
+    const int n = d.n_inst;
+    P.hi.resize(n);
+    P.tab_of.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const hs_instance &in = d.inst[i];
+        int rc = validate_inst(in, err);
+        if (rc) return rc;
+        rc = build_instance(in, P.hi[i], err);
+        if (rc) return rc;
+        if ((d.flags & HS_STOP_ON_AGREEMENT) && in.R < 2) {
+            err = "HS_STOP_ON_AGREEMENT needs R >= 2";
+            return HS_EINVAL;
+        }
+        // share tables between instances with the same ladder
+        int found = -1;
+        for (size_t t = 0; t < P.ht.size(); ++t)
+            if (P.ht[t].K == in.K && std::memcmp(P.ht[t].beta.data(), in.beta, sizeof(double) * in.K) == 0) {
+                found = int(t);
+                break;
+            }
+        if (found < 0) {
+            P.ht.emplace_back();
+            build_tables(in.K, in.beta, P.ht.back());
+            if (P.ht.back().ts_full.size() > (size_t(1) << 24)) {
+                err = "temperature ladder too dense for the exchange tables";
+                return HS_EUNSUPPORTED;
+            }
+            found = int(P.ht.size()) - 1;
+        }
+        P.tab_of[i] = found;
+        P.ncell_max = std::max(P.ncell_max, P.hi[i].ncell);
+        P.K_max = std::max(P.K_max, in.K);
+    }
+    // workspace image: [InstDev][TableDev][order][queue][per-instance data][tables]
+    std::vector<uint32_t> &img = P.image;
+    img.clear();
+    P.idev.resize(n);
+    P.tdev.resize(P.ht.size());
+    P.off_inst = 0;
+    img.resize(align16w(sizeof(InstDev) * n / 4 + 4));
+    P.off_tabs = img.size();
+    img.resize(align16w(P.off_tabs + sizeof(TableDev) * P.tdev.size() / 4 + 4));
+    P.off_order = img.size();
+    img.resize(align16w(P.off_order + n + 4));
+    P.off_queue = img.size();
+    img.resize(align16w(P.off_queue + 4));
+    int64_t spin_off = 0;
+    for (int i = 0; i < n; ++i) {
+        const hs_instance &in = d.inst[i];
+        InstDev &x = P.idev[i];
+        std::memset(&x, 0, sizeof(x));
+        x.L = in.L;
+        x.ncell = in.L * in.L;
+        x.npairs = (x.ncell + 1) / 2;
+        x.K = in.K;
+        x.R = in.R;
+        x.nlanes = in.K * in.R;
+        x.n_sites = 8 * in.L * in.L;
+        x.tab = P.tab_of[i];
+        x.key0 = in.instance_id;
+        x.key1 = d.seed;
+        x.spin_off = spin_off;
+        spin_off += x.n_sites;
+        x.jw_off = int64_t(append(img, P.hi[i].jw.data(), P.hi[i].jw.size()));
+        x.live_off = int64_t(append(img, P.hi[i].live.data(), P.hi[i].live.size()));
+        x.edge_off = int64_t(append(img, P.hi[i].edges.data(), P.hi[i].edges.size()));
+        x.n_live_edges = int32_t(P.hi[i].edges.size());
+        x.cost = int64_t(x.ncell);
+    }
+    for (size_t t = 0; t < P.ht.size(); ++t) {
+        const HostTables &h = P.ht[t];
+        TableDev &x = P.tdev[t];
+        std::memset(&x, 0, sizeof(x));
+        x.K = h.K;
+        x.lds_ts_entries = int32_t(h.ts_hi.size());
+        x.thi_off = int64_t(append(img, h.thi.data(), h.thi.size()));
+        x.tfull_off = int64_t(append(img, h.tfull.data(), h.tfull.size()));
+        x.ts_row_off = int64_t(append(img, h.ts_row.data(), h.ts_row.size()));
+        x.ts_dhi_off = int64_t(append(img, h.ts_dhi.data(), h.ts_dhi.size()));
+        x.ts_dmax_off = int64_t(append(img, h.ts_dmax.data(), h.ts_dmax.size()));
+        x.ts_hi_off = int64_t(append(img, h.ts_hi.data(), h.ts_hi.size()));
+        x.ts_full_off = int64_t(append(img, h.ts_full.data(), h.ts_full.size()));
+        x.ts_full_row_off = int64_t(append(img, h.ts_full_row.data(), h.ts_full_row.size()));
+        P.tshi_max = std::max(P.tshi_max, int(h.ts_hi.size()));
+    }
+    if (size_t(P.tshi_max) * 2 > kLdsTsBudget) {
+        P.lds_ts_ok = 0;
+        P.tshi_max = 0;
+    }
+    // order: most expensive first
+    P.order.resize(n);
+    std::iota(P.order.begin(), P.order.end(), 0);
+    std::stable_sort(P.order.begin(), P.order.end(),
+                     [&](int a, int b) { return P.idev[a].cost > P.idev[b].cost; });
+    std::memcpy(img.data() + P.off_inst, P.idev.data(), sizeof(InstDev) * n);
+    std::memcpy(img.data() + P.off_tabs, P.tdev.data(), sizeof(TableDev) * P.tdev.size());
+    std::memcpy(img.data() + P.off_order, P.order.data(), sizeof(int32_t) * n);
+    P.total_words = align16w(img.size());
+    img.resize(P.total_words, 0u);
+    return HS_OK;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(HS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t _e = (expr);                        \
+        if (_e != hipSuccess) return hip_fail(_e, #expr); \
+    } while (0)
+
+int device_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
+    }
+    return cus;
+}
+
+int choose_waves(const hs_pt_desc &d, const Plan &P)
+{
+    if (d.block_waves > 0) return d.block_waves;
+    // one wavefront per pair of cells of the largest instance, up to 16
+    int pairs = (P.ncell_max + 1) / 2;
+    int w = 1;
+    while (w < pairs && w < 16) w *= 2;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pt_workspace_bytes(const hs_pt_desc *d, size_t *bytes)
+{
+    if (d == nullptr || bytes == nullptr) return fail(HS_EINVAL, "pt_workspace_bytes: NULL argument");
+    Plan P;
+    std::string err;
+    int rc = make_plan(*d, P, err);
+    if (rc) return fail(rc, "pt_workspace_bytes: " + err);
+    *bytes = P.total_words * 4;
+    return HS_OK;
+}
+
+int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
+{
+    if (out == nullptr || d == nullptr || b == nullptr) return fail(HS_EINVAL, "pt_init: NULL argument");
+    *out = nullptr;
+    Plan P;
+    std::string err;
+    int rc = make_plan(*d, P, err);
+    if (rc) return fail(rc, "pt_init: " + err);
+    if (d->n_inst > 0 && (b->spins == nullptr || b->perm == nullptr || b->energy == nullptr ||
+                          b->emin == nullptr || b->thit == nullptr || b->swap_acc == nullptr ||
+                          b->t == nullptr || b->stopped == nullptr || b->workspace == nullptr))
+        return fail(HS_EINVAL, "pt_init: NULL device buffer");
+    if (b->workspace_bytes < P.total_words * 4)
+        return fail(HS_ENOSPACE, "pt_init: workspace too small (need " + std::to_string(P.total_words * 4) +
+                                     " bytes)");
+    auto h = new hs_pt();
+    h->n_inst = d->n_inst;
+    h->buf = *b;
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    h->flags = d->flags;
+    h->swap_interval = d->swap_interval;
+    h->nwaves = choose_waves(*d, P);
+    h->ncell_max = P.ncell_max;
+    h->K_max = std::max(P.K_max, 1);
+    h->tshi_max = P.tshi_max;
+    h->lds_ts_ok = P.lds_ts_ok;
+    h->off_inst = P.off_inst;
+    h->off_tabs = P.off_tabs;
+    h->off_order = P.off_order;
+    h->off_queue = P.off_queue;
+    h->lds_bytes = dev::lds_layout(h->ncell_max, h->K_max, h->tshi_max).total;
+    h->host_ws = std::move(P.image);
+    if (h->n_inst == 0) {
+        *out = h;
+        return HS_OK;
+    }
+    hipError_t e = hipMemcpyAsync(b->workspace, h->host_ws.data(), h->host_ws.size() * 4,
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "pt_init: upload");
+    }
+    const char *ws = reinterpret_cast<const char *>(b->workspace);
+    dev::InitArgs ia;
+    ia.inst = reinterpret_cast<const InstDev *>(ws + h->off_inst * 4);
+    ia.ws32 = reinterpret_cast<const uint32_t *>(ws);
+    ia.spins = b->spins;
+    ia.perm = b->perm;
+    ia.energy = b->energy;
+    ia.emin = b->emin;
+    ia.thit = b->thit;
+    ia.swap_acc = b->swap_acc;
+    ia.t = b->t;
+    ia.stopped = b->stopped;
+    ia.from_buffer = (d->flags & HS_INIT_FROM_BUFFER) ? 1 : 0;
+    hipLaunchKernelGGL(dev::k_pt_init, dim3(h->n_inst), dim3(64), 0, h->stream, ia);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "pt_init: launch");
+    }
+    if (h->lds_bytes > 64 * 1024) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&dev::k_pt_sweep),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(h->lds_bytes));
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "pt_init: LDS size");
+        }
+    }
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&dev::k_pt_sweep),
+                                                     h->nwaves * 64, h->lds_bytes);
+    if (e != hipSuccess || per_cu < 1) {
+        delete h;
+        return fail(HS_EUNSUPPORTED, "pt_init: instances too large for one workgroup's LDS");
+    }
+    h->grid = std::min(h->n_inst, per_cu * device_cus());
+    *out = h;
+    return HS_OK;
+}
+
+int pt_sweep(hs_pt *h, int64_t n_sweeps)
+{
+    if (h == nullptr || n_sweeps < 0) return fail(HS_EINVAL, "pt_sweep: bad arguments");
+    if (h->n_inst == 0 || n_sweeps == 0) return HS_OK;
+    char *ws = reinterpret_cast<char *>(h->buf.workspace);
+    dev::SweepArgs a;
+    a.inst = reinterpret_cast<const InstDev *>(ws + h->off_inst * 4);
+    a.tabs = reinterpret_cast<const TableDev *>(ws + h->off_tabs * 4);
+    a.ws32 = reinterpret_cast<const uint32_t *>(ws);
+    a.order = reinterpret_cast<const int32_t *>(ws + h->off_order * 4);
+    a.queue = reinterpret_cast<uint32_t *>(ws + h->off_queue * 4);
+    a.spins = h->buf.spins;
+    a.perm = h->buf.perm;
+    a.energy = h->buf.energy;
+    a.emin = h->buf.emin;
+    a.thit = h->buf.thit;
+    a.swap_acc = h->buf.swap_acc;
+    a.t = h->buf.t;
+    a.stopped = h->buf.stopped;
+    a.n_inst = h->n_inst;
+    a.swap_interval = h->swap_interval;
+    a.n_sweeps = n_sweeps;
+    a.flags = h->flags;
+    a.ncell_max = h->ncell_max;
+    a.K_max = h->K_max;
+    a.tshi_max = h->tshi_max;
+    a.lds_ts_ok = h->lds_ts_ok;
+    hipLaunchKernelGGL(dev::k_reset_queue, dim3(1), dim3(1), 0, h->stream, a.queue);
+    hipLaunchKernelGGL(dev::k_pt_sweep, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, h->stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "pt_sweep: launch");
+    return HS_OK;
+}
+
+int pt_swap(hs_pt *h)
+{
+    if (h == nullptr) return fail(HS_EINVAL, "pt_swap: NULL handle");
+    if (h->n_inst == 0) return HS_OK;
+    char *ws = reinterpret_cast<char *>(h->buf.workspace);
+    const size_t lds = dev::lds_layout(0, 1, 0).total;
+    hipLaunchKernelGGL(dev::k_swap_extra, dim3(h->n_inst), dim3(64), lds, h->stream,
+                       reinterpret_cast<const InstDev *>(ws + h->off_inst * 4),
+                       reinterpret_cast<const TableDev *>(ws + h->off_tabs * 4),
+                       reinterpret_cast<const uint32_t *>(ws), h->buf.perm, h->buf.energy,
+                       h->buf.swap_acc, h->buf.t, 0, 1, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "pt_swap: launch");
+    return HS_OK;
+}
+
+int pt_measure(hs_pt *h, int32_t *recomputed, int32_t *n_mismatch)
+{
+    if (h == nullptr || recomputed == nullptr) return fail(HS_EINVAL, "pt_measure: bad arguments");
+    if (n_mismatch) *n_mismatch = 0;
+    if (h->n_inst == 0) return HS_OK;
+    char *ws = reinterpret_cast<char *>(h->buf.workspace);
+    // mismatch counter lives in the queue slot's neighbour word
+    int32_t *mm = reinterpret_cast<int32_t *>(ws + h->off_queue * 4) + 1;
+    hipLaunchKernelGGL(dev::k_reset_queue, dim3(1), dim3(1), 0, h->stream, reinterpret_cast<uint32_t *>(mm));
+    hipLaunchKernelGGL(dev::k_energy, dim3(h->n_inst), dim3(64), 0, h->stream,
+                       reinterpret_cast<const InstDev *>(ws + h->off_inst * 4),
+                       reinterpret_cast<const uint32_t *>(ws), h->buf.spins, h->buf.energy, recomputed, mm);
+    HIP_TRY(hipGetLastError());
+    int32_t host_mm = 0;
+    HIP_TRY(hipMemcpyAsync(&host_mm, mm, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (n_mismatch) *n_mismatch = host_mm;
+    if (host_mm != 0) return fail(HS_EMISMATCH, "pt_measure: incremental and recomputed energies differ");
+    return HS_OK;
+}
+
+int pt_destroy(hs_pt *h)
+{
+    delete h;
+    return HS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+"""The C-ABI library loads, exports every declared entry point, and its
+host-only functions agree with the oracle (no GPU needed)."""
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hardspin.h")
+
+
+def _hs():
+    import paper_1605_03607_amd as hs
+    if not os.path.exists(hs.LIB_PATH):
+        pytest.skip("libhardspin.so not built")
+    return hs
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:int|const char \*)\s*\**\s*([a-z_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for want in ("pt_init", "pt_sweep", "pt_swap", "pt_measure", "instance_mutate",
+                 "hardness_eval", "pt_destroy", "hs_last_error", "pt_workspace_bytes",
+                 "hs_version"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    hs = _hs()
+    out = subprocess.run(["nm", "-D", "--defined-only", hs.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in _declared_functions() if n not in exported]
+    assert not missing, missing
+    lib = hs.lib()
+    assert lib.hs_version() >= 10000
+    for n in _declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_library_has_gfx950_code():
+    hs = _hs()
+    # the embedded offload bundle names its target
+    data = open(hs.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in data
+
+
+@pytest.mark.parametrize("alphabet", ["pm1", "pm7"])
+def test_instance_mutate_matches_oracle(alphabet):
+    hs = _hs()
+    L = 4
+    A = workloads.ALPHABETS[alphabet]
+    J = workloads.couplings(L, alphabet, 3, 0)
+    live = workloads.missing_mask(L, 0.02, 3, 0)
+    inst = dict(L=L, J=J, live=live)
+    for step in range(300):
+        for prop in (0, 5, 15):
+            got = hs.instance_mutate(inst, A, 11, 2016, step, prop)
+            want = oracle.mutate(L, live, J, A, 11, 2016, step, prop)
+            assert got == want
+
+
+def test_rao_accept_matches_oracle():
+    hs = _hs()
+    rng = np.random.default_rng(4)
+    cases = [(1.0, 2.0), (2.0, 1.0), (3.0, 2.5), (math.inf, 4.0), (4.0, math.inf),
+             (math.inf, math.inf)]
+    for cur, new in cases:
+        for w in rng.integers(0, 2 ** 32, size=200):
+            assert hs.rao_accept(cur, new, 0.5, int(w)) == oracle.rao_accept(cur, new, 0.5, int(w))
+
+
+def test_invalid_descriptors_are_rejected():
+    hs = _hs()
+    import ctypes as C
+    base = dict(L=4, J=workloads.couplings(4, "pm1", 1, 0), live=None, K=4, R=2,
+                beta=workloads.geometric_betas(0.1, 1.0, 4), instance_id=0)
+    bad = [
+        dict(base, L=17),                        # L > 16
+        dict(base, K=40, R=2),                   # K R > 64
+        dict(base, beta=np.array([0.1, 0.2, 0.2, 0.3])),  # not strictly ascending
+        dict(base, beta=np.array([-0.1, 0.2, 0.3, 0.4])),
+        dict(base, J=np.full(352, 9, np.int8)),  # |J| > 7
+    ]
+    for inst in bad:
+        hi = hs._HostInstances([inst])
+        desc = hs.hs_pt_desc(1, C.cast(hi.arr, C.POINTER(hs.hs_instance)), 1, 1, 0, 0)
+        nb = C.c_size_t(0)
+        rc = hs.lib().pt_workspace_bytes(C.byref(desc), C.byref(nb))
+        assert rc in (-1, -3), inst
+        assert hs.lib().hs_last_error()
+    hi = hs._HostInstances([dict(base, R=1)])
+    desc = hs.hs_pt_desc(1, C.cast(hi.arr, C.POINTER(hs.hs_instance)), 1, 1,
+                         hs.HS_STOP_ON_AGREEMENT, 0)
+    nb = C.c_size_t(0)
+    assert hs.lib().pt_workspace_bytes(C.byref(desc), C.byref(nb)) == -1
+
+
+def test_workspace_grows_with_batch():
+    hs = _hs()
+    import ctypes as C
+    sizes = []
+    for n in (1, 4, 16):
+        insts = workloads.make_batch(workloads.batch_c8(), n)
+        hi = hs._HostInstances(insts)
+        desc = hs.hs_pt_desc(n, C.cast(hi.arr, C.POINTER(hs.hs_instance)), 1, 10, 0, 0)
+        nb = C.c_size_t(0)
+        assert hs.lib().pt_workspace_bytes(C.byref(desc), C.byref(nb)) == 0
+        sizes.append(nb.value)
+    assert sizes[0] < sizes[1] < sizes[2]
