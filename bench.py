@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--block-waves", type=int, default=0)
+    p.add_argument("--probe", action="store_true",
+                   help="also measure instruction issue rates (libhsprobe.so)")
     return p.parse_args()
 
 
@@ -145,6 +147,8 @@ def main():
                      "slots_per_attempt": A_SLOTS},
         "energy_mismatches": mism,
     }
+    if args.probe:
+        out["isa_probe_lane_ops_per_s"] = hs.probe_rates()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, insts, args.cpu_seconds)
     batch.close()

@@ -94,6 +94,25 @@ def lib():
     return _lib
 
 
+PROBE_NAMES = ["v_add_u32", "v_bitop3_b32", "v_mad_u64_u32", "v_mul_hi_u32", "v_mul_lo_u32",
+               "v_dot4_i32_i8", "v_mad_i32_i24"]
+
+
+def probe_rates(iters=2000):
+    """Measured lane-ops/s of each instruction class (libhsprobe.so)."""
+    torch = _torch()
+    path = os.path.join(HERE, "libhsprobe.so")
+    P = C.CDLL(path)
+    P.hs_probe_rate.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_void_p]
+    scratch = torch.zeros(16, dtype=torch.int32, device="cuda")
+    out = {}
+    for w, name in enumerate(PROBE_NAMES):
+        r = C.c_double(0)
+        _check(P.hs_probe_rate(w, iters, C.byref(r), C.c_void_p(scratch.data_ptr())))
+        out[name] = r.value
+    return out
+
+
 def exported_symbols():
     return ["hs_version", "hs_last_error", "pt_workspace_bytes", "pt_init", "pt_sweep", "pt_swap",
             "pt_measure", "pt_destroy", "instance_mutate", "hs_rao_accept",
