@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--block-waves", type=int, default=0)
+    p.add_argument("--copy-mib", type=int, default=0,
+                   help="after the timed steps, run one plain device copy of this many MiB "
+                        "(reference kernel for scaling HBM byte counters)")
     p.add_argument("--probe", action="store_true",
                    help="also measure instruction issue rates (libhsprobe.so)")
     return p.parse_args()
@@ -120,6 +123,13 @@ def main():
     wall = time.perf_counter() - t0
     kernel_ms = [a.elapsed_time(b) for a, b in ev]
     mism = batch.measure()
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ms_per_step = wall * 1e3 / args.steps
     value = attempts_per_step * args.steps / wall
     k_avg_s = float(np.mean(kernel_ms)) / 1e3

@@ -125,7 +125,7 @@ int build_instance(const hs_instance &in, HostInstance &out, std::string &err)
                 const int rb = u == 0 ? r + 1 : r, cb = u == 0 ? c : c + 1;
                 for (int k = 0; k < 4; ++k) {
                     const int i = sid(L, r, c, u, k);
-                    if (live(i)) lm |= 1u << k;
+                    if (live(i)) lm |= 0xFEu << (8 * k);
                     uint32_t jin = 0;
                     for (int k2 = 0; k2 < 4; ++k2)
                         jin = put_byte(jin, k2, -4 * coupling(i, sid(L, r, c, 1 - u, k2)));
@@ -146,6 +146,40 @@ int build_instance(const hs_instance &in, HostInstance &out, std::string &err)
             }
         }
     return HS_OK;
+}
+
+// Wavefront task table of an L x L lattice processed by nwaves wavefronts:
+// wavefront w, phase p, iteration i updates cell pair j = w + i nwaves
+// (cells 2j, 2j+1 in row-major order).  Entry (8 words): Philox counter word
+// (j << 1 | p), quad indices q0 | q1 << 16 (q1 = 0xFFFF without a second
+// cell), then for each cell the spin rows own | opposite << 16 and
+// neighbour A | neighbour B << 16 (row 2 L^2 is the zero row).
+void build_tasks(int L, int nwaves, std::vector<uint32_t> &out, int &iters)
+{
+    const int ncell = L * L, npairs = (ncell + 1) / 2, zero = 2 * ncell;
+    iters = (npairs + nwaves - 1) / nwaves;
+    out.assign(size_t(nwaves) * 2 * iters * 8, 0u);
+    for (int w = 0; w < nwaves; ++w)
+        for (int p = 0; p < 2; ++p)
+            for (int it = 0; it < iters; ++it) {
+                const int j = w + it * nwaves;
+                if (j >= npairs) continue;
+                uint32_t *e = &out[((size_t(w) * 2 + p) * iters + it) * 8];
+                e[0] = (uint32_t(j) << 1) | uint32_t(p);
+                uint32_t qs[2] = {0xFFFFu, 0xFFFFu};
+                for (int h = 0; h < 2; ++h) {
+                    const int cell = 2 * j + h;
+                    if (cell >= ncell) continue;
+                    const int r = cell / L, c = cell % L, u = (r + c + p) & 1;
+                    const int own = cell * 2 + u, oth = cell * 2 + 1 - u;
+                    const int a = u == 0 ? (r > 0 ? (cell - L) * 2 : zero) : (c > 0 ? (cell - 1) * 2 + 1 : zero);
+                    const int b = u == 0 ? (r + 1 < L ? (cell + L) * 2 : zero) : (c + 1 < L ? (cell + 1) * 2 + 1 : zero);
+                    qs[h] = uint32_t(own);
+                    e[2 + 2 * h] = uint32_t(own) | (uint32_t(oth) << 16);
+                    e[3 + 2 * h] = uint32_t(a) | (uint32_t(b) << 16);
+                }
+                e[1] = qs[0] | (qs[1] << 16);
+            }
 }
 
 uint64_t metro_threshold(double beta, int m)

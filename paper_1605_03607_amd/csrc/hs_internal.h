@@ -32,9 +32,10 @@ struct alignas(16) InstDev {
     uint32_t key0, key1;
     int64_t spin_off;   // first uint64 spin word of this instance in buffers.spins
     int64_t jw_off;     // uint32 offset of the coupling words [ncell][2][8]
-    int64_t live_off;   // uint32 offset of the live masks [ncell][2] (bit k)
+    int64_t live_off;   // uint32 offset of the flip masks [ncell][2] (byte k = 0xFE if site k is live)
     int64_t edge_off;   // uint32 offset of packed live couplers (i | j << 12 | (J & 0xff) << 24)
-    int32_t n_live_edges, pad0;
+    int32_t n_live_edges, task_iters;  // task_iters: pair iterations per wavefront and phase
+    int64_t task_off;   // uint32 offset of the wavefront task table of this lattice size
     int64_t cost;       // sweeps x cells, used to order the work queue
 };
 
@@ -68,7 +69,7 @@ struct HostTables {
 struct HostInstance {
     int L = 0, N = 0, E = 0, ncell = 0;
     std::vector<uint32_t> jw;    // [ncell][2][8]
-    std::vector<uint32_t> live;  // [ncell][2]
+    std::vector<uint32_t> live;  // [ncell][2] flip masks: byte k = 0xFE if site k is live
     std::vector<uint32_t> edges; // packed live couplers
 };
 
@@ -76,6 +77,7 @@ struct HostInstance {
 void chimera_edges(int L, std::vector<int32_t> &ei, std::vector<int32_t> &ej);
 int build_instance(const hs_instance &in, HostInstance &out, std::string &err);
 void build_tables(int K, const double *beta, HostTables &out);
+void build_tasks(int L, int nwaves, std::vector<uint32_t> &out, int &iters);
 uint64_t metro_threshold(double beta, int m);
 uint64_t swap_threshold(double beta_lo, double beta_hi, int64_t d);
 void philox_host(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

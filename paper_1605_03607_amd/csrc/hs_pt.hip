@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -38,12 +39,38 @@ constexpr uint32_t M1 = 0xCD9E8D57u;
 constexpr uint32_t W0 = 0x9E3779B9u;
 constexpr uint32_t W1 = 0xBB67AE85u;
 
-// a ^ b ^ k in one v_bitop3_b32 (truth table 0x96); k must be wave-uniform.
+// a ^ b ^ k in one v_bitop3_b32 (truth table 0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k)
 {
     uint32_t d;
-    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "v"(k));
     return d;
+}
+
+// Read-only workspace data through the constant address space: uniform
+// addresses then compile to scalar loads (the workspace is never written while
+// a kernel reads it).
+template <class T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <class T>
+__device__ __forceinline__ cptr<T> to_const(const T *p)
+{
+    return (cptr<T>)(p);
+}
+
+// A descriptor copied word by word through scalar loads.
+template <class T>
+__device__ __forceinline__ T load_desc(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "descriptor size");
+    const cptr<uint32_t> src = (cptr<uint32_t>)(p);
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (int i = 0; i < int(sizeof(T) / 4); ++i) w[i] = src[i];
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
 }
 
 __device__ __forceinline__ void mul_hilo(uint32_t a, uint32_t b, uint32_t &hi, uint32_t &lo)
@@ -53,9 +80,34 @@ __device__ __forceinline__ void mul_hilo(uint32_t a, uint32_t b, uint32_t &hi, u
     lo = uint32_t(p);
 }
 
-// Rounds r0..9 (0-based) of Philox4x32-10 on state x with base key (k0, k1).
+// A wave-uniform value held in a vector register (keeps scalar registers
+// free; v_bitop3 reads three vector operands without a constant-bus slot).
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t s)
+{
+    uint32_t v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(__builtin_amdgcn_readfirstlane(s)));
+    return v;
+}
+
+// The ten round keys of Philox4x32-10 for key (k0, k1): (k0 + r W0, k1 + r W1).
+struct RoundKeys {
+    uint32_t a[10], b[10];
+};
+
+__device__ __forceinline__ RoundKeys round_keys(uint32_t k0, uint32_t k1)
+{
+    RoundKeys K;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        K.a[r] = in_vgpr(k0 + uint32_t(r) * W0);
+        K.b[r] = in_vgpr(k1 + uint32_t(r) * W1);
+    }
+    return K;
+}
+
+// Rounds r0..9 (0-based) of Philox4x32-10 on state x.
 __device__ __forceinline__ void philox_rounds(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3,
-                                              uint32_t k0, uint32_t k1, int r0)
+                                              const RoundKeys &K, int r0)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
@@ -63,8 +115,8 @@ __device__ __forceinline__ void philox_rounds(uint32_t &x0, uint32_t &x1, uint32
         uint32_t h0, l0, h1, l1;
         mul_hilo(x0, M0, h0, l0);
         mul_hilo(x2, M1, h1, l1);
-        const uint32_t n0 = xor3(h1, x1, k0 + uint32_t(r) * W0);
-        const uint32_t n2 = xor3(h0, x3, k1 + uint32_t(r) * W1);
+        const uint32_t n0 = xor3(h1, x1, K.a[r]);
+        const uint32_t n2 = xor3(h0, x3, K.b[r]);
         x0 = n0;
         x1 = l1;
         x2 = n2;
@@ -75,7 +127,8 @@ __device__ __forceinline__ void philox_rounds(uint32_t &x0, uint32_t &x1, uint32
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1)
 {
-    philox_rounds(c0, c1, c2, c3, k0, k1, 0);
+    const RoundKeys K = round_keys(k0, k1);
+    philox_rounds(c0, c1, c2, c3, K, 0);
     return make_uint4(c0, c1, c2, c3);
 }
 
@@ -109,13 +162,13 @@ struct MetroLane {
 };
 
 __device__ __forceinline__ uint4 metro_call(const MetroLane &ml, const MetroUniform &mu, uint32_t c1,
-                                            uint32_t k0, uint32_t k1)
+                                            const RoundKeys &K)
 {
     const uint32_t x0 = ml.a ^ c1;
     uint32_t qh, ql;
     mul_hilo(x0, M0, qh, ql);
     uint32_t y0 = ml.lo ^ mu.y0u, y1 = mu.y1, y2 = qh ^ mu.y2u, y3 = ql;
-    philox_rounds(y0, y1, y2, y3, k0, k1, 2);
+    philox_rounds(y0, y1, y2, y3, K, 2);
     return make_uint4(y0, y1, y2, y3);
 }
 
@@ -135,7 +188,7 @@ __device__ __forceinline__ int wave_min(int v)
 // ---------------------------------------------------------------------------
 // Dynamic LDS layout of the sweep kernel.
 struct LdsLayout {
-    uint32_t S, zero, thi, tshi, E, perm, slot, emin, thit, sacc, udraw, misc, total;
+    uint32_t S, thl, thi, tshi, E, perm, slot, emin, thit, sacc, udraw, misc, total;
 };
 
 __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int K_max, int tshi_max)
@@ -143,9 +196,9 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int K_max, int ts
     LdsLayout l;
     uint32_t o = 0;
     l.S = o;
-    o += uint32_t(ncell_max) * 2 * 64 * 4;
-    l.zero = o;
-    o += 64 * 4;
+    o += (uint32_t(ncell_max) * 2 + 1) * 64 * 4;  // spin rows, then one zero row
+    l.thl = o;
+    o += uint32_t(kMRow) * 64 * 4;
     l.thi = o;
     o += uint32_t(K_max) * kMRow * 4;
     l.tshi = o;
@@ -254,6 +307,118 @@ __device__ void exchange_pass(uint32_t t, uint32_t use, int K, int R, uint32_t k
     }
 }
 
+// After sweep t (wavefront 0 only): exchange pass when due, running minima
+// per replica set, agreement stop flag (misc[1]).  Its descriptors are
+// reloaded each time, not held in registers across the sweep.
+__device__ __forceinline__ int opaque(int v)
+{
+    int o;
+    asm volatile("s_mov_b32 %0, %1" : "=s"(o) : "s"(v));
+    return o;
+}
+
+__device__ __forceinline__ void sweep_epilogue(const SweepArgs &a, int n_in, int64_t t, char *lds)
+{
+    const LdsLayout L = lds_layout(a.ncell_max, a.K_max, a.tshi_max);
+    const int lane = threadIdx.x & 63;
+    const int n = opaque(n_in);  // keeps the descriptor loads inside the sweep loop
+    const InstDev d = a.inst[n];
+    const int K = d.K, R = d.R, nlanes = d.nlanes;
+    int32_t *E = reinterpret_cast<int32_t *>(lds + L.E);
+    int32_t *emin = reinterpret_cast<int32_t *>(lds + L.emin);
+    int64_t *thit = reinterpret_cast<int64_t *>(lds + L.thit);
+    int32_t *misc = reinterpret_cast<int32_t *>(lds + L.misc);
+    if (a.swap_interval > 0 && ((t + 1) % a.swap_interval) == 0)
+        exchange_pass(uint32_t(t), kUseSwap, K, R, d.key0, d.key1, a.tabs[d.tab], a.ws32, lds, L,
+                      a.lds_ts_ok != 0);
+    const int ev = lane < nlanes ? E[lane] : INT32_MAX;
+    int agree = 1;
+    int64_t tmax = 0;
+    int em0 = 0;
+    for (int r = 0; r < R; ++r) {
+        const bool mine = lane >= r * K && lane < (r + 1) * K;
+        const int mn = wave_min(mine ? ev : INT32_MAX);
+        int em = emin[r];
+        int64_t th = thit[r];
+        if (mn < em) {
+            em = mn;
+            th = t + 1;
+            if (lane == 0) {
+                emin[r] = em;
+                thit[r] = th;
+            }
+        }
+        if (r == 0) em0 = em;
+        if (em != em0) agree = 0;
+        tmax = th > tmax ? th : tmax;
+    }
+    const bool stop_mode = (a.flags & HS_STOP_ON_AGREEMENT) != 0;
+    if (lane == 0) misc[1] = (stop_mode && agree && (t + 1) >= 2 * tmax) ? 1 : 0;
+}
+
+// Quad table entry: LDS byte offsets of the spin rows of an updated cell
+// side (own), of the opposite side of its cell (oth) and of the same side of
+// the two neighbouring cells along that side's direction (a, b; the zero
+// row when absent), plus the side's index q for the coupling words.
+struct QuadRows {
+    uint32_t own, oth, a, b;
+};
+
+__host__ __device__ inline QuadRows quad_rows(int cell, int p, int Lc, int ncell)
+{
+    const int r = cell / Lc, c = cell - r * Lc;
+    const int u = (r + c + p) & 1;
+    const int zero = ncell * 2;
+    QuadRows x;
+    x.own = uint32_t(cell * 2 + u) * 256u;
+    x.oth = uint32_t(cell * 2 + 1 - u) * 256u;
+    x.a = uint32_t(u == 0 ? (r > 0 ? (cell - Lc) * 2 : zero) : (c > 0 ? (cell - 1) * 2 + 1 : zero)) * 256u;
+    x.b = uint32_t(u == 0 ? (r + 1 < Lc ? (cell + Lc) * 2 : zero) : (c + 1 < Lc ? (cell + 1) * 2 + 1 : zero)) *
+          256u;
+    return x;
+}
+
+// Dot products and the spin multiply use the compiler builtins, not inline
+// assembly: the wait states a dot-instruction result needs before a dependent
+// read are inserted only for instructions the compiler itself generates.
+__device__ __forceinline__ int dot4_0(uint32_t a, uint32_t b)
+{
+    return __builtin_amdgcn_sdot4(int(a), int(b), 0, false);
+}
+
+__device__ __forceinline__ int dot4_acc(uint32_t a, uint32_t b, int c)
+{
+    return __builtin_amdgcn_sdot4(int(a), int(b), c, false);
+}
+
+// (sign-extended byte K of own) * h4
+template <int K>
+__device__ __forceinline__ int mul_spin(uint32_t own, int h4)
+{
+    return __mul24(int(int8_t(uint8_t(own >> (8 * K)))), h4);
+}
+
+// 4 m = 2 dE of site k of a cell side: h4 = -4 h from the opposite side
+// (coupling bytes jin) and the two inter-cell neighbours (perm'd word xv,
+// coupling bytes jv); m4 = s h4.
+template <int K>
+__device__ __forceinline__ int site_m4(uint32_t own, uint32_t oth, uint32_t xv, uint32_t jin, uint32_t jv)
+{
+    return mul_spin<K>(own, dot4_acc(oth, jin, dot4_0(xv, jv)));
+}
+
+// Per-lane threshold columns: THL[m + 42][lane] = fast threshold of the
+// lane's current temperature, so the per-site gather is bank-conflict free.
+__device__ __forceinline__ void refresh_thresholds(uint32_t *THL, const uint32_t *thi, const int32_t *slot,
+                                                   int K, int tid, int nthreads)
+{
+    for (int i = tid; i < kMRow * 64; i += nthreads) {
+        const int m = i >> 6, l = i & 63;
+        const int k = min(slot[l] & 0xFF, K - 1);
+        THL[i] = thi[k * kMRow + m];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // The persistent sweep kernel.
 __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
@@ -274,8 +439,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
     uint32_t *sacc = reinterpret_cast<uint32_t *>(lds + L.sacc);
     int32_t *misc = reinterpret_cast<int32_t *>(lds + L.misc);
     uint16_t *tshi = reinterpret_cast<uint16_t *>(lds + L.tshi);
-
-    reinterpret_cast<uint32_t *>(lds + L.zero)[lane] = 0u;
+    uint32_t *THL = reinterpret_cast<uint32_t *>(lds + L.thl);
 
     for (;;) {
         if (tid == 0) misc[0] = int32_t(atomicAdd(a.queue, 1u));
@@ -283,13 +447,14 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         const int qi = __builtin_amdgcn_readfirstlane(misc[0]);
         __syncthreads();
         if (qi >= a.n_inst) break;
-        const int n = __builtin_amdgcn_readfirstlane(a.order[qi]);
-        const InstDev d = a.inst[n];
-        const TableDev tb = a.tabs[d.tab];
+        const int n = __builtin_amdgcn_readfirstlane(to_const(a.order)[qi]);
+        const InstDev d = load_desc(a.inst + n);
+        const TableDev tb = load_desc(a.tabs + d.tab);
         const int K = d.K, R = d.R, nlanes = d.nlanes, ncell = d.ncell, Lc = d.L;
         const uint32_t key0 = d.key0, key1 = d.key1;
-        const uint32_t *jw = a.ws32 + d.jw_off;
-        const uint32_t *livew = a.ws32 + d.live_off;
+        const cptr<uint32_t> ws4 = to_const(a.ws32);
+        const cptr<uint32_t> jw = ws4 + d.jw_off;     // coupling words [ncell][2][8]
+        const cptr<uint32_t> livew = ws4 + d.live_off; // flip masks [ncell][2]
         const uint64_t *sp = a.spins + d.spin_off;
 
         // ---- load state ----
@@ -299,11 +464,12 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint64_t word = sp[q * 4 + k];
-                const uint32_t bit = ((lm >> k) & 1u) ? uint32_t((word >> lane) & 1ull) : 0u;
+                const uint32_t bit = ((lm >> (8 * k + 1)) & 1u) ? uint32_t((word >> lane) & 1ull) : 0u;
                 w |= (bit ? 0xFFu : 0x01u) << (8 * k);
             }
             S[q * 64 + lane] = w;
         }
+        if (wave == 0) S[ncell * 2 * 64 + lane] = 0u;  // zero row for absent neighbours
         for (int i = tid; i < K * kMRow; i += blockDim.x) thi[i] = a.ws32[tb.thi_off + i];
         if (a.lds_ts_ok) {
             const uint32_t *src = a.ws32 + tb.ts_hi_off;
@@ -311,6 +477,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             for (int i = tid; i < (tb.lds_ts_entries + 1) / 2; i += blockDim.x) dst[i] = src[i];
         }
         if (tid < 64) {
+            slot[tid] = 0;
             E[tid] = a.energy[n * 64 + tid];
             perm[tid] = a.perm[n * 64 + tid];
             emin[tid] = a.emin[n * 64 + tid];
@@ -325,14 +492,23 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         }
         __syncthreads();
 
+        refresh_thresholds(THL, thi, slot, K, tid, blockDim.x);
+        __syncthreads();
+
         int64_t t = a.t[n];
-        const bool stop_mode = (a.flags & HS_STOP_ON_AGREEMENT) != 0;
         bool stopped = __builtin_amdgcn_readfirstlane(misc[1]) != 0;
         const int npairs = d.npairs;
+        const int iters = d.task_iters;
+        const cptr<uint32_t> task = ws4 + d.task_off;
+        const uint32_t lane4 = uint32_t(lane) * 4u;
+        // per-lane threshold column of THL, entry m at byte m * 256
+        const uint32_t thl_base = L.thl + uint32_t(kMaxM) * 256u + lane4;
+        const uint32_t s_base = L.S + lane4;
+        const RoundKeys RK = round_keys(key0, key1);
 
         for (int64_t s = 0; s < a.n_sweeps && !stopped; ++s) {
             const uint32_t tt = uint32_t(t);
-            // per-lane slot state
+            // per-lane slot state (changes only after exchange passes)
             const int sl = slot[lane];
             const int kslot = min(sl & 0xFF, K - 1);
             const uint32_t sword = (uint32_t(sl & 0xFF) << 8) | uint32_t(sl >> 8);
@@ -344,137 +520,111 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                 ml.lo = l;
             }
             const MetroUniform mu = metro_uniform(tt, kUseMetroHi, key0, key1);
-            const uint32_t thi_base = L.thi + uint32_t(kslot * kMRow + kMaxM) * 4u;
-            const uint32_t *tfull = a.ws32 + tb.tfull_off + kslot * kMRow + kMaxM;
             int e4 = 0;
 
             for (int p = 0; p < 2; ++p) {
-                for (int j = wave; j < npairs; j += nwaves) {
-                    const uint32_t c1 = (uint32_t(j) << 1) | uint32_t(p);
-                    const uint4 rw = metro_call(ml, mu, c1, key0, key1);
+                for (int it = 0; it < iters; ++it) {
+                    if (wave + it * nwaves >= npairs) break;
+                    // task entry: counter word, quad indices, spin rows (scalar loads)
+                    const cptr<uint32_t> te = task + ((wave * 2 + p) * iters + it) * 8;
+                    const uint32_t c1 = te[0];
+                    const uint32_t qq = te[1];
+                    const bool second = (qq >> 16) != 0xFFFFu;
+                    const uint4 rw = metro_call(ml, mu, c1, RK);
+                    uint32_t own[2], nw[2], orow[2];
                     const int e4_save = e4;
-                    uint32_t own_orig[2], own_new[2];
-                    int qflag = 0;
-                    const int ncq = (2 * j + 1 < ncell) ? 2 : 1;
-                    // fast pass: decide on the high 16 bits
-                    for (int h = 0; h < ncq; ++h) {
-                        const int cell = 2 * j + h;
-                        const int r = cell / Lc, c = cell - r * Lc;
-                        const int u = (r + c + p) & 1;
-                        const int q = cell * 2 + u;
-                        const int na = u == 0 ? (r > 0 ? cell - Lc : -1) : (c > 0 ? cell - 1 : -1);
-                        const int nb = u == 0 ? (r + 1 < Lc ? cell + Lc : -1) : (c + 1 < Lc ? cell + 1 : -1);
-                        const uint32_t own = S[q * 64 + lane];
-                        const uint32_t oth = S[(cell * 2 + 1 - u) * 64 + lane];
-                        const uint32_t A = na >= 0 ? S[(na * 2 + u) * 64 + lane] : 0u;
-                        const uint32_t B = nb >= 0 ? S[(nb * 2 + u) * 64 + lane] : 0u;
+                    uint32_t tmin = 0xFFFFFFFFu;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t roo = te[2 + 2 * h], rab = te[3 + 2 * h];
+                        const uint32_t q = (h == 0 || !second) ? (qq & 0xFFFFu) : (qq >> 16);
+                        const cptr<uint32_t> jq = jw + q * 8;
+                        const uint32_t fm = livew[q];
+                        orow[h] = s_base + ((roo & 0xFFFFu) << 8);
+                        const uint32_t o0 = *reinterpret_cast<const uint32_t *>(lds + orow[h]);
+                        const uint32_t oth = *reinterpret_cast<const uint32_t *>(lds + s_base + ((roo >> 16) << 8));
+                        const uint32_t A = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab & 0xFFFFu) << 8));
+                        const uint32_t B = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab >> 16) << 8));
                         const uint32_t x01 = __builtin_amdgcn_perm(B, A, 0x05040100u);
                         const uint32_t x23 = __builtin_amdgcn_perm(B, A, 0x07060302u);
-                        const uint32_t *jq = jw + q * 8;
-                        const uint32_t lm = livew[q];
-                        uint32_t nw = own;
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const uint32_t xv = k < 2 ? x01 : x23;
-                            const int h4 = __builtin_amdgcn_sdot4(int(oth), int(jq[k]),
-                                                                  __builtin_amdgcn_sdot4(int(xv), int(jq[4 + k]), 0, false),
-                                                                  false);
-                            const int sgn = int(int8_t(uint8_t(own >> (8 * k))));
-                            const int m4 = __mul24(sgn, h4);
-                            const uint32_t th = *reinterpret_cast<const uint32_t *>(lds + thi_base + m4);
-                            const uint32_t u16 = half16(rw, 4 * h + k);
-                            const bool live = (lm >> k) & 1u;
-                            const bool acc = live && (u16 <= th);
-                            qflag |= int(live && u16 == th);
-                            nw ^= acc ? (0xFEu << (8 * k)) : 0u;
-                            e4 += acc ? m4 : 0;
-                        }
-                        own_orig[h] = own;
-                        own_new[h] = nw;
+                        const int m0 = site_m4<0>(o0, oth, x01, jq[0], jq[4]);
+                        const int m1 = site_m4<1>(o0, oth, x01, jq[1], jq[5]);
+                        const int m2 = site_m4<2>(o0, oth, x23, jq[2], jq[6]);
+                        const int m3 = site_m4<3>(o0, oth, x23, jq[3], jq[7]);
+                        const uint32_t t0 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m0 * 64);
+                        const uint32_t t1 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m1 * 64);
+                        const uint32_t t2 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m2 * 64);
+                        const uint32_t t3 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m3 * 64);
+                        const uint32_t wlo = h == 0 ? rw.x : rw.z;
+                        const uint32_t whi = h == 0 ? rw.y : rw.w;
+                        // d = thi - u16: accept iff d >= 0, tie iff d == 0
+                        const int d0 = int(t0) - int(wlo & 0xFFFFu), d1 = int(t1) - int(wlo >> 16);
+                        const int d2 = int(t2) - int(whi & 0xFFFFu), d3 = int(t3) - int(whi >> 16);
+                        tmin = min(tmin, min(min(uint32_t(d0), uint32_t(d1)), min(uint32_t(d2), uint32_t(d3))));
+                        const int s0 = d0 >> 31, s1 = d1 >> 31, s2 = d2 >> 31, s3 = d3 >> 31;  // -1 = reject
+                        const int de = (m0 & ~s0) + (m1 & ~s1) + (m2 & ~s2) + (m3 & ~s3);
+                        if (h == 0 || second) e4 += de;
+                        // reject bytes R (0xFF where rejected); flip = ~R & fm (fm = 0xFE per live site)
+                        const uint32_t r01 = __builtin_amdgcn_perm(uint32_t(s1), uint32_t(s0), 0x0c0c0400u);
+                        const uint32_t r23 = __builtin_amdgcn_perm(uint32_t(s3), uint32_t(s2), 0x04000c0cu);
+                        const uint32_t rej = r01 | r23;
+                        own[h] = o0;
+                        nw[h] = o0 ^ (~rej & fm);
                     }
-                    if (__any(qflag)) {
+                    if (__any(tmin == 0u)) {
                         // exact pass for this pair: full 32-bit uniforms
                         const MetroUniform mlo = metro_uniform(tt, kUseMetroLo, key0, key1);
-                        const uint4 rl = metro_call(ml, mlo, c1, key0, key1);
+                        const uint4 rl = metro_call(ml, mlo, c1, RK);
+                        const uint32_t *tfull = a.ws32 + tb.tfull_off + kslot * kMRow + kMaxM;
                         e4 = e4_save;
-                        for (int h = 0; h < ncq; ++h) {
-                            const int cell = 2 * j + h;
-                            const int r = cell / Lc, c = cell - r * Lc;
-                            const int u = (r + c + p) & 1;
-                            const int q = cell * 2 + u;
-                            const int na = u == 0 ? (r > 0 ? cell - Lc : -1) : (c > 0 ? cell - 1 : -1);
-                            const int nb = u == 0 ? (r + 1 < Lc ? cell + Lc : -1) : (c + 1 < Lc ? cell + 1 : -1);
-                            const uint32_t own = own_orig[h];
-                            const uint32_t oth = S[(cell * 2 + 1 - u) * 64 + lane];
-                            const uint32_t A = na >= 0 ? S[(na * 2 + u) * 64 + lane] : 0u;
-                            const uint32_t B = nb >= 0 ? S[(nb * 2 + u) * 64 + lane] : 0u;
+                        for (int h = 0; h < 2; ++h) {
+                            const uint32_t roo = te[2 + 2 * h], rab = te[3 + 2 * h];
+                            const uint32_t q = (h == 0 || !second) ? (qq & 0xFFFFu) : (qq >> 16);
+                            const cptr<uint32_t> jq = jw + q * 8;
+                            const uint32_t oth = *reinterpret_cast<const uint32_t *>(lds + s_base + ((roo >> 16) << 8));
+                            const uint32_t A = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab & 0xFFFFu) << 8));
+                            const uint32_t B = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab >> 16) << 8));
                             const uint32_t x01 = __builtin_amdgcn_perm(B, A, 0x05040100u);
                             const uint32_t x23 = __builtin_amdgcn_perm(B, A, 0x07060302u);
-                            const uint32_t *jq = jw + q * 8;
-                            const uint32_t lm = livew[q];
-                            uint32_t nw = own;
+                            const uint32_t o0 = own[h];
+                            int m[4];
+                            m[0] = site_m4<0>(o0, oth, x01, jq[0], jq[4]);
+                            m[1] = site_m4<1>(o0, oth, x01, jq[1], jq[5]);
+                            m[2] = site_m4<2>(o0, oth, x23, jq[2], jq[6]);
+                            m[3] = site_m4<3>(o0, oth, x23, jq[3], jq[7]);
+                            uint32_t flip = 0;
+                            int de = 0;
                             for (int k = 0; k < 4; ++k) {
-                                const uint32_t xv = k < 2 ? x01 : x23;
-                                const int h4 = __builtin_amdgcn_sdot4(int(oth), int(jq[k]),
-                                                                      __builtin_amdgcn_sdot4(int(xv), int(jq[4 + k]), 0, false),
-                                                                      false);
-                                const int sgn = int(int8_t(uint8_t(own >> (8 * k))));
-                                const int m4 = __mul24(sgn, h4);
                                 const uint32_t uu = (half16(rw, 4 * h + k) << 16) | half16(rl, 4 * h + k);
-                                const bool live = (lm >> k) & 1u;
-                                const bool acc = live && (m4 <= 0 || uu < tfull[m4 >> 2]);
-                                nw ^= acc ? (0xFEu << (8 * k)) : 0u;
-                                e4 += acc ? m4 : 0;
+                                const bool acc = m[k] <= 0 || uu < tfull[m[k] >> 2];
+                                flip |= acc ? (0xFEu << (8 * k)) : 0u;
+                                de += acc ? m[k] : 0;
                             }
-                            own_new[h] = nw;
+                            if (h == 0 || second) e4 += de;
+                            nw[h] = o0 ^ (flip & livew[q]);  // flip bytes 0xFE, fm bytes 0xFE
                         }
                     }
-                    for (int h = 0; h < ncq; ++h) {
-                        const int cell = 2 * j + h;
-                        const int r = cell / Lc, c = cell - r * Lc;
-                        const int u = (r + c + p) & 1;
-                        S[(cell * 2 + u) * 64 + lane] = own_new[h];
-                    }
+                    *reinterpret_cast<uint32_t *>(lds + orow[0]) = nw[0];
+                    if (second) *reinterpret_cast<uint32_t *>(lds + orow[1]) = nw[1];
                 }
                 __syncthreads();
             }
             // ---- energies, running minima, exchange, agreement ----
             if (lane < nlanes) atomicAdd(&E[lane], e4 >> 1);
             __syncthreads();
-            if (wave == 0) {
-                if (a.swap_interval > 0 && ((t + 1) % a.swap_interval) == 0)
-                    exchange_pass(tt, kUseSwap, K, R, key0, key1, tb, a.ws32, lds, L, a.lds_ts_ok != 0);
-                const int ev = lane < nlanes ? E[lane] : INT32_MAX;
-                int agree = 1;
-                int64_t tmax = 0;
-                int em0 = 0;
-                for (int r = 0; r < R; ++r) {
-                    const bool mine = lane >= r * K && lane < (r + 1) * K;
-                    const int mn = wave_min(mine ? ev : INT32_MAX);
-                    int em = emin[r];
-                    int64_t th = thit[r];
-                    if (mn < em) {
-                        em = mn;
-                        th = t + 1;
-                        if (lane == 0) {
-                            emin[r] = em;
-                            thit[r] = th;
-                        }
-                    }
-                    if (r == 0) em0 = em;
-                    if (em != em0) agree = 0;
-                    tmax = th > tmax ? th : tmax;
-                }
-                if (lane == 0) misc[1] = (stop_mode && agree && (t + 1) >= 2 * tmax) ? 1 : 0;
-            }
+            if (wave == 0) sweep_epilogue(a, n, t, lds);
             __syncthreads();
-            if (tid < K * R) {
-                const int kk = tid / R, rr = tid % R;
-                slot[perm[tid]] = kk | (rr << 8);
+            if (a.swap_interval > 0 && ((t + 1) % a.swap_interval) == 0) {
+                if (tid < K * R) {
+                    const int kk = tid / R, rr = tid % R;
+                    slot[perm[tid]] = kk | (rr << 8);
+                }
+                __syncthreads();
+                refresh_thresholds(THL, thi, slot, K, tid, blockDim.x);
+                __syncthreads();
             }
             stopped = __builtin_amdgcn_readfirstlane(misc[1]) != 0;
             t += 1;
-            __syncthreads();
         }
 
         // ---- store state ----
@@ -486,7 +636,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint64_t bits = __ballot(((w >> (8 * k)) & 0xFFu) == 0xFFu) & lane_mask;
-                if (lane == k) spw[q * 4 + k] = ((lm >> k) & 1u) ? bits : 0ull;
+                if (lane == k) spw[q * 4 + k] = ((lm >> (8 * k + 1)) & 1u) ? bits : 0ull;
             }
         }
         if (tid < 64) {
@@ -558,7 +708,7 @@ __global__ void __launch_bounds__(64) k_pt_init(InitArgs a)
                 bits = sp[q * 4 + k] & lane_mask;
             else
                 bits = __ballot(lane < nlanes && (ww[k] >> 31) != 0u) & lane_mask;
-            if (!((lm >> k) & 1u)) bits = 0ull;
+            if (!((lm >> (8 * k + 1)) & 1u)) bits = 0ull;
             if (lane == 0) sp[q * 4 + k] = bits;
         }
     }
@@ -653,6 +803,7 @@ struct Plan {
     std::vector<TableDev> tdev;
     std::vector<int32_t> order;
     std::vector<uint32_t> image;  // workspace image in uint32 words
+    int nwaves = 16;
     size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0;
     int ncell_max = 0, K_max = 0, tshi_max = 0;
     int lds_ts_ok = 1;
@@ -742,6 +893,14 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
         P.ncell_max = std::max(P.ncell_max, P.hi[i].ncell);
         P.K_max = std::max(P.K_max, in.K);
     }
+    // wavefronts per workgroup: one per cell pair of the largest instance, up to 16
+    if (d.block_waves > 0) {
+        P.nwaves = d.block_waves;
+    } else {
+        const int pairs = (P.ncell_max + 1) / 2;
+        P.nwaves = 1;
+        while (P.nwaves < pairs && P.nwaves < 16) P.nwaves *= 2;
+    }
     // workspace image: [InstDev][TableDev][order][queue][per-instance data][tables]
     std::vector<uint32_t> &img = P.image;
     img.clear();
@@ -756,6 +915,16 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
     P.off_queue = img.size();
     img.resize(align16w(P.off_queue + 4));
     int64_t spin_off = 0;
+    int64_t task_off[HS_MAX_L + 1];
+    int task_iters[HS_MAX_L + 1];
+    for (int l = 0; l <= HS_MAX_L; ++l) task_off[l] = -1;
+    for (int i = 0; i < n; ++i) {
+        const int Lx = d.inst[i].L;
+        if (task_off[Lx] >= 0) continue;
+        std::vector<uint32_t> tk;
+        build_tasks(Lx, P.nwaves, tk, task_iters[Lx]);
+        task_off[Lx] = int64_t(append(img, tk.data(), tk.size()));
+    }
     for (int i = 0; i < n; ++i) {
         const hs_instance &in = d.inst[i];
         InstDev &x = P.idev[i];
@@ -776,6 +945,8 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
         x.live_off = int64_t(append(img, P.hi[i].live.data(), P.hi[i].live.size()));
         x.edge_off = int64_t(append(img, P.hi[i].edges.data(), P.hi[i].edges.size()));
         x.n_live_edges = int32_t(P.hi[i].edges.size());
+        x.task_off = task_off[in.L];
+        x.task_iters = task_iters[in.L];
         x.cost = int64_t(x.ncell);
     }
     for (size_t t = 0; t < P.ht.size(); ++t) {
@@ -833,16 +1004,6 @@ int device_cus()
     return cus;
 }
 
-int choose_waves(const hs_pt_desc &d, const Plan &P)
-{
-    if (d.block_waves > 0) return d.block_waves;
-    // one wavefront per pair of cells of the largest instance, up to 16
-    int pairs = (P.ncell_max + 1) / 2;
-    int w = 1;
-    while (w < pairs && w < 16) w *= 2;
-    return w;
-}
-
 }  // namespace
 
 extern "C" {
@@ -879,7 +1040,7 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
     h->stream = reinterpret_cast<hipStream_t>(stream);
     h->flags = d->flags;
     h->swap_interval = d->swap_interval;
-    h->nwaves = choose_waves(*d, P);
+    h->nwaves = P.nwaves;
     h->ncell_max = P.ncell_max;
     h->K_max = std::max(P.K_max, 1);
     h->tshi_max = P.tshi_max;
@@ -919,17 +1080,16 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
         delete h;
         return hip_fail(e, "pt_init: launch");
     }
+    const void *kfn = reinterpret_cast<const void *>(&dev::k_pt_sweep);
     if (h->lds_bytes > 64 * 1024) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&dev::k_pt_sweep),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(h->lds_bytes));
+        e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(h->lds_bytes));
         if (e != hipSuccess) {
             delete h;
             return hip_fail(e, "pt_init: LDS size");
         }
     }
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&dev::k_pt_sweep),
-                                                     h->nwaves * 64, h->lds_bytes);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, h->nwaves * 64, h->lds_bytes);
     if (e != hipSuccess || per_cu < 1) {
         delete h;
         return fail(HS_EUNSUPPORTED, "pt_init: instances too large for one workgroup's LDS");
