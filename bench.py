@@ -66,6 +66,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--block-waves", type=int, default=0)
+    p.add_argument("--swap-interval", type=int, default=None,
+                   help="sweeps between exchange passes (default: the workload's)")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed steps, run one plain device copy of this many MiB "
                         "(reference kernel for scaling HBM byte counters)")
@@ -122,6 +124,8 @@ def main():
 
     import paper_1605_03607_amd as hs
     cfg = workloads.batch_c8()
+    if args.swap_interval is not None:
+        cfg["swap_interval"] = args.swap_interval
     sweeps = args.sweeps or cfg["sweeps"]
     insts = workloads.make_batch(cfg)
     n_inst = len(insts)
