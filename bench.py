@@ -2,10 +2,11 @@
 
 Workload: 256 independent Chimera C8 instances (N = 512, 1472 couplers),
 J uniform in {+-1..+-7}, K = 32 temperatures (beta geometric 0.1..5.0) x
-R = 2 replica sets = 64 lanes per instance, an exchange pass after every 10th
-Metropolis sweep (the elementary Monte Carlo step of Sec. III.B).  One step =
-10^5 sweeps of the whole batch (Metropolis sweeps, exchange passes, running
-minima) in one persistent launch, continuing the same chains.
+R = 2 replica sets = 64 lanes per instance, an exchange pass after every
+Metropolis sweep (--swap-interval 10 gives the elementary Monte Carlo step of
+Sec. III.B).  One step = 10^5 sweeps of the whole batch (Metropolis sweeps,
+exchange passes, running minima) in one persistent launch, continuing the
+same chains.
 
 Prints one JSON line (rank 0, N = 1 GPU) with the roofline of the sweep kernel
 (integer VALU issue bound) and the CPU oracle timed on a bounded sample.

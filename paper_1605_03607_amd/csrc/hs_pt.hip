@@ -14,11 +14,15 @@
 //     Metropolis uniforms of the pair's two updated cell sides.  The low
 //     halves come from a second Philox use and are computed only when a lane
 //     ties on the high half (probability 2^-16 per attempt).
-//   * Thresholds: fast table thi[k][m] = T >> 16 (0x10000 for m <= 0) in LDS;
-//     the exact table T = floor(2^32 exp(-2 beta m)) in global memory for ties.
-//   * Exchange passes run in wavefront 0: the acceptance of pair (k, k+1) for
-//     every possible carried configuration is evaluated lane-parallel, then
-//     the sequential ascending pass follows the carried index.
+//   * Thresholds: fast table thi[k][m] = T >> 16 (0x10000 for m <= 0), held
+//     in LDS as one column per slot index k R + r.  The slot indices of the
+//     64 lanes are a permutation, so the per-lane gather is free of bank
+//     conflicts and the table never changes.  The exact table
+//     T = floor(2^32 exp(-2 beta m)) stays in global memory for ties.
+//   * Exchange passes: every wavefront evaluates part of the acceptance tests
+//     of pair (k, k+1) for every configuration that can be carried into slot
+//     k, then one wavefront per replica set links the runs of accepted
+//     exchanges.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -188,35 +192,31 @@ __device__ __forceinline__ int wave_min(int v)
 // ---------------------------------------------------------------------------
 // Dynamic LDS layout of the sweep kernel.
 struct LdsLayout {
-    uint32_t S, thl, thi, tshi, E, perm, slot, emin, thit, sacc, udraw, misc, total;
+    uint32_t S, ths, tshi, Eacc, perm, slot, sacc, xrow, stopv, misc, total;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int K_max, int tshi_max)
+__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max)
 {
     LdsLayout l;
     uint32_t o = 0;
     l.S = o;
     o += (uint32_t(ncell_max) * 2 + 1) * 64 * 4;  // spin rows, then one zero row
-    l.thl = o;
-    o += uint32_t(kMRow) * 64 * 4;
-    l.thi = o;
-    o += uint32_t(K_max) * kMRow * 4;
+    l.ths = o;
+    o += uint32_t(kMRow) * 64 * 4;                // threshold columns by slot index
     l.tshi = o;
     o += ((uint32_t(tshi_max) * 2 + 15) / 16) * 16;
-    l.E = o;
-    o += 64 * 4;
+    l.Eacc = o;
+    o += 2 * 64 * 4;                              // lane energies, double-buffered by sweep parity
     l.perm = o;
     o += 64 * 4;
     l.slot = o;
     o += 64 * 4;
-    l.emin = o;
-    o += 64 * 4;
-    l.thit = o;
-    o += 64 * 8;
     l.sacc = o;
     o += 64 * 4;
-    l.udraw = o;
-    o += 64 * 4;
+    l.xrow = o;
+    o += 4 * 64 * 4;                              // exchange-table rows of pair (k, k+1), k = index
+    l.stopv = o;
+    o += 64 * 64;                                 // run ends of the exchange pass, [set][start]
     l.misc = o;
     o += 16 * 4;
     l.total = o;
@@ -241,119 +241,125 @@ struct SweepArgs {
     int32_t swap_interval;
     int64_t n_sweeps;
     uint32_t flags;
-    int32_t ncell_max, K_max, tshi_max;
+    int32_t ncell_max, tshi_max;
     int32_t lds_ts_ok;        // 1 if every ladder's fast exchange table fits in LDS
 };
 
-// Exchange decision for one candidate (lane-parallel): d = E_x - E_y with x at
-// slot k, y at slot k+1, uniform u.  Exact: d <= 0 or u < floor(2^32 e^{-db d}).
-__device__ __forceinline__ bool swap_accept(int d, uint32_t u, int k, const TableDev &tb,
-                                            const uint32_t *ws32, const uint16_t *tshi_lds,
-                                            bool use_lds)
+// Exchange decision (detailed balance, Sec. II) for configuration x at slot k
+// and y at slot k + 1: d = E_x - E_y, accept iff d <= 0 or
+// u < floor(2^32 exp(-(beta_{k+1} - beta_k) d)).  The 16-bit table decides
+// unless the high halves tie; then the exact 32-bit table does.
+__device__ __forceinline__ bool swap_accept(int d, uint32_t u, int row, int dhi, int dmx, int frow,
+                                            const TableDev &tb, const uint32_t *ws32,
+                                            const uint16_t *tshi_lds, bool use_lds)
 {
     if (d <= 0) return true;
-    const int32_t *row = reinterpret_cast<const int32_t *>(ws32 + tb.ts_row_off);
-    const int32_t *dhi = reinterpret_cast<const int32_t *>(ws32 + tb.ts_dhi_off);
-    const int32_t *dmx = reinterpret_cast<const int32_t *>(ws32 + tb.ts_dmax_off);
-    const int32_t *frow = reinterpret_cast<const int32_t *>(ws32 + tb.ts_full_row_off);
     uint32_t th = 0;
-    if (d <= dhi[k]) {
-        const int at = row[k] + d - 1;
+    if (d <= dhi) {
+        const int at = row + d - 1;
         th = use_lds ? tshi_lds[at] : reinterpret_cast<const uint16_t *>(ws32 + tb.ts_hi_off)[at];
     }
     const uint32_t u16 = u >> 16;
     if (u16 != th) return u16 < th;
-    const uint32_t tf = d <= dmx[k] ? ws32[tb.ts_full_off + frow[k] + d - 1] : 0u;
+    const uint32_t tf = d <= dmx ? ws32[tb.ts_full_off + frow + d - 1] : 0u;
     return u < tf;
 }
 
-// One exchange pass of the current instance, run by wavefront 0.
-__device__ void exchange_pass(uint32_t t, uint32_t use, int K, int R, uint32_t key0, uint32_t key1,
-                              const TableDev &tb, const uint32_t *ws32, char *lds, const LdsLayout &L,
-                              bool use_lds)
+// Exchange-table rows of pair (k, k + 1) for k = 0..K-2: xrow[0..3][k] =
+// start of the 16-bit row, its length, length of the exact row, its start.
+__device__ __forceinline__ void load_xrows(int32_t *xrow, const TableDev &tb, const uint32_t *ws32, int K,
+                                           int i)
+{
+    if (i < 64) {
+        const bool ok = i < K - 1;
+        xrow[i] = ok ? int32_t(ws32[tb.ts_row_off + i]) : 0;
+        xrow[64 + i] = ok ? int32_t(ws32[tb.ts_dhi_off + i]) : 0;
+        xrow[128 + i] = ok ? int32_t(ws32[tb.ts_dmax_off + i]) : 0;
+        xrow[192 + i] = ok ? int32_t(ws32[tb.ts_full_row_off + i]) : 0;
+    }
+}
+
+// An exchange pass is one ascending sweep over the pairs (k, k+1) of each
+// replica set.  The configuration at slot k when pair k is tested is the one
+// that started at the beginning j of the current run of accepted exchanges
+// (a rejection at k starts a new run at k + 1).  Step 1: for every set r and
+// every possible start j, stop(j) = the first pair k >= j rejected when slot
+// k holds the configuration from slot j (K - 1 if none).  All wavefronts
+// share the (K-1) R tests; one lane per pair k, one pass per (r, j).
+__device__ void exchange_stops(uint32_t t, uint32_t use, int K, int R, uint32_t key0, uint32_t key1,
+                               int wave, int nwaves, const int32_t *E, const int32_t *perm,
+                               const int32_t *xrow, uint8_t *stopv, const TableDev &tb,
+                               const uint32_t *ws32, const uint16_t *tshi, bool use_lds)
 {
     const int lane = threadIdx.x & 63;
-    int32_t *E = reinterpret_cast<int32_t *>(lds + L.E);
-    int32_t *perm = reinterpret_cast<int32_t *>(lds + L.perm);
-    uint32_t *sacc = reinterpret_cast<uint32_t *>(lds + L.sacc);
-    const uint16_t *tshi = reinterpret_cast<const uint16_t *>(lds + L.tshi);
-    // draws for every (k, r): lane l = k R + r
+    const int npair = (K - 1) * R;
+    if (wave >= npair) return;
+    // uniform of pair (k, r) in lane k R + r
     uint32_t udraw = 0;
-    if (lane < (K - 1) * R) udraw = philox(t, uint32_t(lane / R), uint32_t(lane % R), use, key0, key1).x;
-    for (int r = 0; r < R; ++r) {
-        const int o = lane < K ? perm[lane * R + r] : 0;
-        const int Eo = lane < K ? E[o] : 0;
-        int newp = o;
-        int c = 0;
-        for (int k = 0; k + 1 < K; ++k) {
-            const uint32_t u = __shfl(udraw, k * R + r, 64);
-            const int Eb = __shfl(Eo, k + 1, 64);
-            bool ok = false;
-            if (lane <= k) ok = swap_accept(Eo - Eb, u, k, tb, ws32, tshi, use_lds);
-            const uint64_t mask = __ballot(ok);
-            const int onext = __shfl(o, k + 1, 64);
-            const int ocar = __shfl(o, c, 64);
-            if ((mask >> c) & 1ull) {
-                if (lane == k) newp = onext;
-                if (lane == 0) sacc[k * R + r] += 1u;
-            } else {
-                if (lane == k) newp = ocar;
-                c = k + 1;
-            }
-        }
-        const int olast = __shfl(o, c, 64);
-        if (lane == K - 1) newp = olast;
-        if (lane < K) perm[lane * R + r] = newp;
+    if (lane < npair) udraw = philox(t, uint32_t(lane / R), uint32_t(lane % R), use, key0, key1).x;
+    const int row = xrow[lane], dhi = xrow[64 + lane], dmx = xrow[128 + lane], frow = xrow[192 + lane];
+    for (int P = wave; P < npair; P += nwaves) {
+        const int r = P % R, j = P / R;
+        const bool valid = lane >= j && lane <= K - 2;
+        const int kc = valid ? lane : j;
+        const int x = perm[j * R + r];
+        const int y = perm[(kc + 1) * R + r];
+        const uint32_t u = __shfl(udraw, kc * R + r, 64);
+        bool rej = false;
+        if (valid) rej = !swap_accept(E[x] - E[y], u, row, dhi, dmx, frow, tb, ws32, tshi, use_lds);
+        const uint64_t m = __ballot(rej);
+        if (lane == 0) stopv[r * 64 + j] = uint8_t(m ? __ffsll((unsigned long long)m) - 1 : K - 1);
     }
 }
 
-// After sweep t (wavefront 0 only): exchange pass when due, running minima
-// per replica set, agreement stop flag (misc[1]).  Its descriptors are
-// reloaded each time, not held in registers across the sweep.
-__device__ __forceinline__ int opaque(int v)
+// Step 2 (wavefront w takes the sets r = w, w + nwaves, ...): follow the run
+// starts 0, stop(0) + 1, ... and apply the pass.  Slot k of a run that starts
+// at j receives the configuration from slot k + 1 if k < stop(j) (accepted)
+// and the carried configuration from slot j if k = stop(j).
+__device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm, int32_t *slot,
+                               uint32_t *sacc, const uint8_t *stopv)
 {
-    int o;
-    asm volatile("s_mov_b32 %0, %1" : "=s"(o) : "s"(v));
-    return o;
-}
-
-__device__ __forceinline__ void sweep_epilogue(const SweepArgs &a, int n_in, int64_t t, char *lds)
-{
-    const LdsLayout L = lds_layout(a.ncell_max, a.K_max, a.tshi_max);
     const int lane = threadIdx.x & 63;
-    const int n = opaque(n_in);  // keeps the descriptor loads inside the sweep loop
-    const InstDev d = a.inst[n];
-    const int K = d.K, R = d.R, nlanes = d.nlanes;
-    int32_t *E = reinterpret_cast<int32_t *>(lds + L.E);
-    int32_t *emin = reinterpret_cast<int32_t *>(lds + L.emin);
-    int64_t *thit = reinterpret_cast<int64_t *>(lds + L.thit);
-    int32_t *misc = reinterpret_cast<int32_t *>(lds + L.misc);
-    if (a.swap_interval > 0 && ((t + 1) % a.swap_interval) == 0)
-        exchange_pass(uint32_t(t), kUseSwap, K, R, d.key0, d.key1, a.tabs[d.tab], a.ws32, lds, L,
-                      a.lds_ts_ok != 0);
-    const int ev = lane < nlanes ? E[lane] : INT32_MAX;
-    int agree = 1;
-    int64_t tmax = 0;
-    int em0 = 0;
-    for (int r = 0; r < R; ++r) {
-        const bool mine = lane >= r * K && lane < (r + 1) * K;
-        const int mn = wave_min(mine ? ev : INT32_MAX);
-        int em = emin[r];
-        int64_t th = thit[r];
-        if (mn < em) {
-            em = mn;
-            th = t + 1;
-            if (lane == 0) {
-                emin[r] = em;
-                thit[r] = th;
-            }
+    for (int r = wave; r < R; r += nwaves) {
+        const int sv = lane < K - 1 ? int(stopv[r * 64 + lane]) : K - 1;
+        uint64_t starts = 0;
+        int s = 0;
+        for (;;) {
+            starts |= 1ull << s;
+            if (s >= K - 1) break;
+            const int nx = __builtin_amdgcn_readlane(sv, s) + 1;
+            if (nx > K - 1) break;
+            s = nx;
         }
-        if (r == 0) em0 = em;
-        if (em != em0) agree = 0;
-        tmax = th > tmax ? th : tmax;
+        const uint64_t below = lane == 63 ? starts : (starts & ((2ull << lane) - 1ull));
+        const int jk = 63 - __clzll((long long)below);  // start of the run holding slot `lane`
+        const int st = __shfl(sv, jk, 64);
+        const int oj = perm[jk * R + r];
+        const int on = perm[min(lane + 1, K - 1) * R + r];
+        const int np = lane == st ? oj : on;
+        if (lane < K) {
+            perm[lane * R + r] = np;
+            slot[np] = lane | (r << 8);
+            if (lane < K - 1 && lane != st) sacc[lane * R + r] += 1u;
+        }
     }
-    const bool stop_mode = (a.flags & HS_STOP_ON_AGREEMENT) != 0;
-    if (lane == 0) misc[1] = (stop_mode && agree && (t + 1) >= 2 * tmax) ? 1 : 0;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_max64(int64_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const int64_t w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
 }
 
 // Quad table entry: LDS byte offsets of the spin rows of an updated cell
@@ -407,39 +413,36 @@ __device__ __forceinline__ int site_m4(uint32_t own, uint32_t oth, uint32_t xv, 
     return mul_spin<K>(own, dot4_acc(oth, jin, dot4_0(xv, jv)));
 }
 
-// Per-lane threshold columns: THL[m + 42][lane] = fast threshold of the
-// lane's current temperature, so the per-site gather is bank-conflict free.
-__device__ __forceinline__ void refresh_thresholds(uint32_t *THL, const uint32_t *thi, const int32_t *slot,
-                                                   int K, int tid, int nthreads)
-{
-    for (int i = tid; i < kMRow * 64; i += nthreads) {
-        const int m = i >> 6, l = i & 63;
-        const int k = min(slot[l] & 0xFF, K - 1);
-        THL[i] = thi[k * kMRow + m];
-    }
-}
-
 // ---------------------------------------------------------------------------
 // The persistent sweep kernel.
+//
+// Per sweep: colour phase 0, barrier, colour phase 1, barrier.  Every coupler
+// joins a colour-0 and a colour-1 site, so the energy after the sweep is
+// sum over colour-1 sites of s_i' h_i (Eq. 1), with h_i the local field seen
+// in phase 1 and s_i' the spin after its update: phase 1 alone yields the
+// lane energies, accumulated in LDS with atomics.  Every wavefront then keeps
+// its own copy of the running minima (identical in all wavefronts) and, when
+// an exchange pass is due, the two exchange steps add two barriers.
 __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
 {
     extern __shared__ __align__(16) char lds[];
-    const LdsLayout L = lds_layout(a.ncell_max, a.K_max, a.tshi_max);
+    const LdsLayout L = lds_layout(a.ncell_max, a.tshi_max);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nwaves = __builtin_amdgcn_readfirstlane(int(blockDim.x >> 6));
     uint32_t *S = reinterpret_cast<uint32_t *>(lds + L.S);
-    uint32_t *thi = reinterpret_cast<uint32_t *>(lds + L.thi);
-    int32_t *E = reinterpret_cast<int32_t *>(lds + L.E);
+    uint32_t *THS = reinterpret_cast<uint32_t *>(lds + L.ths);
+    int32_t *Eacc = reinterpret_cast<int32_t *>(lds + L.Eacc);
     int32_t *perm = reinterpret_cast<int32_t *>(lds + L.perm);
     int32_t *slot = reinterpret_cast<int32_t *>(lds + L.slot);
-    int32_t *emin = reinterpret_cast<int32_t *>(lds + L.emin);
-    int64_t *thit = reinterpret_cast<int64_t *>(lds + L.thit);
     uint32_t *sacc = reinterpret_cast<uint32_t *>(lds + L.sacc);
+    int32_t *xrow = reinterpret_cast<int32_t *>(lds + L.xrow);
+    uint8_t *stopv = reinterpret_cast<uint8_t *>(lds + L.stopv);
     int32_t *misc = reinterpret_cast<int32_t *>(lds + L.misc);
     uint16_t *tshi = reinterpret_cast<uint16_t *>(lds + L.tshi);
-    uint32_t *THL = reinterpret_cast<uint32_t *>(lds + L.thl);
+    const bool stop_mode = (a.flags & HS_STOP_ON_AGREEMENT) != 0;
+    const int si = a.swap_interval;
 
     for (;;) {
         if (tid == 0) misc[0] = int32_t(atomicAdd(a.queue, 1u));
@@ -450,7 +453,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         const int n = __builtin_amdgcn_readfirstlane(to_const(a.order)[qi]);
         const InstDev d = load_desc(a.inst + n);
         const TableDev tb = load_desc(a.tabs + d.tab);
-        const int K = d.K, R = d.R, nlanes = d.nlanes, ncell = d.ncell, Lc = d.L;
+        const int K = d.K, R = d.R, nlanes = d.nlanes, ncell = d.ncell;
         const uint32_t key0 = d.key0, key1 = d.key1;
         const cptr<uint32_t> ws4 = to_const(a.ws32);
         const cptr<uint32_t> jw = ws4 + d.jw_off;     // coupling words [ncell][2][8]
@@ -470,18 +473,21 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             S[q * 64 + lane] = w;
         }
         if (wave == 0) S[ncell * 2 * 64 + lane] = 0u;  // zero row for absent neighbours
-        for (int i = tid; i < K * kMRow; i += blockDim.x) thi[i] = a.ws32[tb.thi_off + i];
+        // threshold column of slot index k R + r holds the row of temperature k
+        for (int i = tid; i < kMRow * 64; i += blockDim.x) {
+            const int m = i >> 6, sx = i & 63;
+            const int k = sx < nlanes ? sx / R : 0;
+            THS[i] = a.ws32[tb.thi_off + k * kMRow + m];
+        }
         if (a.lds_ts_ok) {
             const uint32_t *src = a.ws32 + tb.ts_hi_off;
             uint32_t *dst = reinterpret_cast<uint32_t *>(tshi);
             for (int i = tid; i < (tb.lds_ts_entries + 1) / 2; i += blockDim.x) dst[i] = src[i];
         }
+        load_xrows(xrow, tb, a.ws32, K, tid);
         if (tid < 64) {
             slot[tid] = 0;
-            E[tid] = a.energy[n * 64 + tid];
             perm[tid] = a.perm[n * 64 + tid];
-            emin[tid] = a.emin[n * 64 + tid];
-            thit[tid] = a.thit[n * 64 + tid];
             sacc[tid] = a.swap_acc[n * 64 + tid];
         }
         if (tid == 0) misc[1] = a.stopped[n];
@@ -492,26 +498,39 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         }
         __syncthreads();
 
-        refresh_thresholds(THL, thi, slot, K, tid, blockDim.x);
-        __syncthreads();
+        // per-lane state every wavefront keeps (identical in all of them)
+        const bool live = lane < nlanes;
+        int Ecur = live ? a.energy[n * 64 + lane] : 0;
+        const int set = live ? lane / K : 0;
+        const int seg_lo = set * K, seg_hi = seg_lo + K;
+        int em = a.emin[n * 64 + set];
+        int64_t th = a.thit[n * 64 + set];
+        int agree = 0;
+        int64_t tmax = 0;
+        if (stop_mode) {
+            agree = wave_min(live ? em : INT32_MAX) == wave_max(live ? em : INT32_MIN);
+            tmax = wave_max64(live ? th : int64_t(0));
+        }
 
         int64_t t = a.t[n];
         bool stopped = __builtin_amdgcn_readfirstlane(misc[1]) != 0;
+        // sweeps left until the next exchange pass (0: after this sweep)
+        int cd = si > 0 ? int((int64_t(si) - (t + 1) % si) % si) : -1;
         const int npairs = d.npairs;
         const int iters = d.task_iters;
         const cptr<uint32_t> task = ws4 + d.task_off;
-        const uint32_t lane4 = uint32_t(lane) * 4u;
-        // per-lane threshold column of THL, entry m at byte m * 256
-        const uint32_t thl_base = L.thl + uint32_t(kMaxM) * 256u + lane4;
-        const uint32_t s_base = L.S + lane4;
+        const uint32_t s_base = L.S + uint32_t(lane) * 4u;
         const RoundKeys RK = round_keys(key0, key1);
 
-        for (int64_t s = 0; s < a.n_sweeps && !stopped; ++s) {
+        for (int64_t sw = 0; sw < a.n_sweeps && !stopped; ++sw) {
             const uint32_t tt = uint32_t(t);
-            // per-lane slot state (changes only after exchange passes)
+            // per-lane slot state (changes only in exchange passes)
             const int sl = slot[lane];
             const int kslot = min(sl & 0xFF, K - 1);
+            const uint32_t sidx = live ? uint32_t(kslot * R + (sl >> 8)) : uint32_t(lane);
             const uint32_t sword = (uint32_t(sl & 0xFF) << 8) | uint32_t(sl >> 8);
+            // threshold column of this lane's slot, entry m at byte m * 256
+            const uint32_t thl_base = L.ths + uint32_t(kMaxM) * 256u + sidx * 4u;
             MetroLane ml;
             {
                 uint32_t h, l;
@@ -520,8 +539,12 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                 ml.lo = l;
             }
             const MetroUniform mu = metro_uniform(tt, kUseMetroHi, key0, key1);
-            int e4 = 0;
+            int32_t *Eb = Eacc + (tt & 1u) * 64u;
+            if (wave == 0) Eb[lane] = 0;
+            int e4 = 0;        // phase 1: sum of (m4 ^ s) over this wavefront's sites
+            uint32_t nrej = 0; // phase 1: 8 x rejected sites
 
+#pragma unroll
             for (int p = 0; p < 2; ++p) {
                 for (int it = 0; it < iters; ++it) {
                     if (wave + it * nwaves >= npairs) break;
@@ -533,6 +556,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     const uint4 rw = metro_call(ml, mu, c1, RK);
                     uint32_t own[2], nw[2], orow[2];
                     const int e4_save = e4;
+                    const uint32_t nrej_save = nrej;
                     uint32_t tmin = 0xFFFFFFFFu;
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
@@ -562,12 +586,15 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         const int d2 = int(t2) - int(whi & 0xFFFFu), d3 = int(t3) - int(whi >> 16);
                         tmin = min(tmin, min(min(uint32_t(d0), uint32_t(d1)), min(uint32_t(d2), uint32_t(d3))));
                         const int s0 = d0 >> 31, s1 = d1 >> 31, s2 = d2 >> 31, s3 = d3 >> 31;  // -1 = reject
-                        const int de = (m0 & ~s0) + (m1 & ~s1) + (m2 & ~s2) + (m3 & ~s3);
-                        if (h == 0 || second) e4 += de;
                         // reject bytes R (0xFF where rejected); flip = ~R & fm (fm = 0xFE per live site)
                         const uint32_t r01 = __builtin_amdgcn_perm(uint32_t(s1), uint32_t(s0), 0x0c0c0400u);
                         const uint32_t r23 = __builtin_amdgcn_perm(uint32_t(s3), uint32_t(s2), 0x04000c0cu);
                         const uint32_t rej = r01 | r23;
+                        if (p == 1 && (h == 0 || second)) {
+                            // (m4 ^ s) - s = m4 if accepted, -m4 if rejected
+                            e4 += (m0 ^ s0) + (m1 ^ s1) + (m2 ^ s2) + (m3 ^ s3);
+                            nrej += __builtin_popcount(rej);
+                        }
                         own[h] = o0;
                         nw[h] = o0 ^ (~rej & fm);
                     }
@@ -577,6 +604,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         const uint4 rl = metro_call(ml, mlo, c1, RK);
                         const uint32_t *tfull = a.ws32 + tb.tfull_off + kslot * kMRow + kMaxM;
                         e4 = e4_save;
+                        nrej = nrej_save;
                         for (int h = 0; h < 2; ++h) {
                             const uint32_t roo = te[2 + 2 * h], rab = te[3 + 2 * h];
                             const uint32_t q = (h == 0 || !second) ? (qq & 0xFFFFu) : (qq >> 16);
@@ -593,37 +621,53 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                             m[2] = site_m4<2>(o0, oth, x23, jq[2], jq[6]);
                             m[3] = site_m4<3>(o0, oth, x23, jq[3], jq[7]);
                             uint32_t flip = 0;
-                            int de = 0;
+                            int ev = 0;
                             for (int k = 0; k < 4; ++k) {
                                 const uint32_t uu = (half16(rw, 4 * h + k) << 16) | half16(rl, 4 * h + k);
                                 const bool acc = m[k] <= 0 || uu < tfull[m[k] >> 2];
                                 flip |= acc ? (0xFEu << (8 * k)) : 0u;
-                                de += acc ? m[k] : 0;
+                                ev += acc ? m[k] : -m[k];
                             }
-                            if (h == 0 || second) e4 += de;
+                            if (p == 1 && (h == 0 || second)) e4 += ev;
                             nw[h] = o0 ^ (flip & livew[q]);  // flip bytes 0xFE, fm bytes 0xFE
                         }
                     }
                     *reinterpret_cast<uint32_t *>(lds + orow[0]) = nw[0];
                     if (second) *reinterpret_cast<uint32_t *>(lds + orow[1]) = nw[1];
                 }
+                if (p == 1 && live) atomicAdd(&Eb[lane], (e4 + int(nrej >> 3)) >> 2);
                 __syncthreads();
             }
-            // ---- energies, running minima, exchange, agreement ----
-            if (lane < nlanes) atomicAdd(&E[lane], e4 >> 1);
-            __syncthreads();
-            if (wave == 0) sweep_epilogue(a, n, t, lds);
-            __syncthreads();
-            if (a.swap_interval > 0 && ((t + 1) % a.swap_interval) == 0) {
-                if (tid < K * R) {
-                    const int kk = tid / R, rr = tid % R;
-                    slot[perm[tid]] = kk | (rr << 8);
+            // ---- lane energies, running minima, agreement, exchange ----
+            Ecur = Eb[lane];
+            if (__any(live && Ecur < em)) {
+                // minimum over the lane's replica set (lanes seg_lo .. seg_hi - 1)
+                int v = live ? Ecur : INT32_MAX;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int w = __shfl(v, (lane + o) & 63, 64);
+                    if (lane + o < seg_hi) v = min(v, w);
                 }
+                const int mn = __shfl(v, seg_lo, 64);
+                if (live && mn < em) {
+                    em = mn;
+                    th = t + 1;
+                }
+                if (stop_mode) {
+                    agree = wave_min(live ? em : INT32_MAX) == wave_max(live ? em : INT32_MIN);
+                    tmax = wave_max64(live ? th : int64_t(0));
+                }
+            }
+            const bool stop_now = stop_mode && agree && (t + 1) >= 2 * tmax;
+            if (cd == 0) {
+                exchange_stops(tt, kUseSwap, K, R, key0, key1, wave, nwaves, Eb, perm, xrow, stopv, tb,
+                               a.ws32, tshi, a.lds_ts_ok != 0);
                 __syncthreads();
-                refresh_thresholds(THL, thi, slot, K, tid, blockDim.x);
+                exchange_apply(K, R, wave, nwaves, perm, slot, sacc, stopv);
                 __syncthreads();
             }
-            stopped = __builtin_amdgcn_readfirstlane(misc[1]) != 0;
+            if (si > 0) cd = cd == 0 ? si - 1 : cd - 1;
+            stopped = stop_now;
             t += 1;
         }
 
@@ -639,16 +683,21 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                 if (lane == k) spw[q * 4 + k] = ((lm >> (8 * k + 1)) & 1u) ? bits : 0ull;
             }
         }
-        if (tid < 64) {
-            a.energy[n * 64 + tid] = tid < nlanes ? E[tid] : 0;
-            a.perm[n * 64 + tid] = uint8_t(perm[tid]);
-            a.emin[n * 64 + tid] = emin[tid];
-            a.thit[n * 64 + tid] = thit[tid];
-            a.swap_acc[n * 64 + tid] = sacc[tid];
-        }
-        if (tid == 0) {
-            a.t[n] = t;
-            a.stopped[n] = stopped ? 1 : 0;
+        if (wave == 0) {
+            const int head = min(lane, R - 1) * K;
+            const int emh = __shfl(em, head, 64);
+            const int64_t thh = __shfl(th, head, 64);
+            a.energy[n * 64 + lane] = live ? Ecur : 0;
+            a.perm[n * 64 + lane] = uint8_t(perm[lane]);
+            a.swap_acc[n * 64 + lane] = sacc[lane];
+            if (lane < R) {
+                a.emin[n * 64 + lane] = emh;
+                a.thit[n * 64 + lane] = thh;
+            }
+            if (lane == 0) {
+                a.t[n] = t;
+                a.stopped[n] = stopped ? 1 : 0;
+            }
         }
         __syncthreads();
     }
@@ -743,26 +792,28 @@ __global__ void __launch_bounds__(64) k_energy(const InstDev *inst, const uint32
     if (lane < d.nlanes && ev != energy[n * 64 + lane]) atomicAdd(mismatch, 1);
 }
 
-// One extra exchange pass per instance (pt_swap).
+// One extra exchange pass per instance (pt_swap), one wavefront each.
 __global__ void __launch_bounds__(64) k_swap_extra(const InstDev *inst, const TableDev *tabs,
                                                    const uint32_t *ws32, uint8_t *perm_g,
                                                    const int32_t *energy, uint32_t *swap_acc,
-                                                   const int64_t *t, int ncell_max, int K_max,
-                                                   int tshi_max)
+                                                   const int64_t *t)
 {
-    extern __shared__ __align__(16) char lds[];
-    const LdsLayout L = lds_layout(ncell_max, K_max, tshi_max);
+    __shared__ int32_t E[64], perm[64], slot[64], xrow[256];
+    __shared__ uint32_t sacc[64];
+    __shared__ uint8_t stopv[64 * 64];
     const int n = blockIdx.x, lane = threadIdx.x;
     const InstDev d = inst[n];
     const TableDev tb = tabs[d.tab];
-    int32_t *E = reinterpret_cast<int32_t *>(lds + L.E);
-    int32_t *perm = reinterpret_cast<int32_t *>(lds + L.perm);
-    uint32_t *sacc = reinterpret_cast<uint32_t *>(lds + L.sacc);
     E[lane] = energy[n * 64 + lane];
     perm[lane] = perm_g[n * 64 + lane];
     sacc[lane] = swap_acc[n * 64 + lane];
+    slot[lane] = 0;
+    load_xrows(xrow, tb, ws32, d.K, lane);
     __syncthreads();
-    exchange_pass(uint32_t(t[n]), kUseSwapExtra, d.K, d.R, d.key0, d.key1, tb, ws32, lds, L, false);
+    exchange_stops(uint32_t(t[n]), kUseSwapExtra, d.K, d.R, d.key0, d.key1, 0, 1, E, perm, xrow, stopv, tb,
+                   ws32, nullptr, false);
+    __syncthreads();
+    exchange_apply(d.K, d.R, 0, 1, perm, slot, sacc, stopv);
     __syncthreads();
     perm_g[n * 64 + lane] = uint8_t(perm[lane]);
     swap_acc[n * 64 + lane] = sacc[lane];
@@ -783,7 +834,7 @@ struct hs_pt {
     int32_t swap_interval = 0;
     int nwaves = 16;
     int grid = 0;
-    int ncell_max = 0, K_max = 0, tshi_max = 0;
+    int ncell_max = 0, tshi_max = 0;
     int lds_ts_ok = 1;
     size_t lds_bytes = 0;
     // workspace layout (byte offsets)
@@ -794,6 +845,7 @@ struct hs_pt {
 namespace {
 
 constexpr size_t kLdsTsBudget = 48 * 1024;  // bytes of LDS for the 16-bit exchange table
+constexpr size_t kLdsLimit = 160 * 1024;    // LDS of one gfx950 workgroup
 
 struct Plan {
     std::vector<HostInstance> hi;
@@ -965,9 +1017,14 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
         x.ts_full_row_off = int64_t(append(img, h.ts_full_row.data(), h.ts_full_row.size()));
         P.tshi_max = std::max(P.tshi_max, int(h.ts_hi.size()));
     }
-    if (size_t(P.tshi_max) * 2 > kLdsTsBudget) {
+    if (size_t(P.tshi_max) * 2 > kLdsTsBudget ||
+        dev::lds_layout(P.ncell_max, P.tshi_max).total > kLdsLimit) {
         P.lds_ts_ok = 0;
         P.tshi_max = 0;
+    }
+    if (dev::lds_layout(P.ncell_max, 0).total > kLdsLimit) {
+        err = "instance too large for one workgroup's LDS";
+        return HS_EUNSUPPORTED;
     }
     // order: most expensive first
     P.order.resize(n);
@@ -1042,14 +1099,13 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
     h->swap_interval = d->swap_interval;
     h->nwaves = P.nwaves;
     h->ncell_max = P.ncell_max;
-    h->K_max = std::max(P.K_max, 1);
     h->tshi_max = P.tshi_max;
     h->lds_ts_ok = P.lds_ts_ok;
     h->off_inst = P.off_inst;
     h->off_tabs = P.off_tabs;
     h->off_order = P.off_order;
     h->off_queue = P.off_queue;
-    h->lds_bytes = dev::lds_layout(h->ncell_max, h->K_max, h->tshi_max).total;
+    h->lds_bytes = dev::lds_layout(h->ncell_max, h->tshi_max).total;
     h->host_ws = std::move(P.image);
     if (h->n_inst == 0) {
         *out = h;
@@ -1123,7 +1179,6 @@ int pt_sweep(hs_pt *h, int64_t n_sweeps)
     a.n_sweeps = n_sweeps;
     a.flags = h->flags;
     a.ncell_max = h->ncell_max;
-    a.K_max = h->K_max;
     a.tshi_max = h->tshi_max;
     a.lds_ts_ok = h->lds_ts_ok;
     hipLaunchKernelGGL(dev::k_reset_queue, dim3(1), dim3(1), 0, h->stream, a.queue);
@@ -1138,12 +1193,11 @@ int pt_swap(hs_pt *h)
     if (h == nullptr) return fail(HS_EINVAL, "pt_swap: NULL handle");
     if (h->n_inst == 0) return HS_OK;
     char *ws = reinterpret_cast<char *>(h->buf.workspace);
-    const size_t lds = dev::lds_layout(0, 1, 0).total;
-    hipLaunchKernelGGL(dev::k_swap_extra, dim3(h->n_inst), dim3(64), lds, h->stream,
+    hipLaunchKernelGGL(dev::k_swap_extra, dim3(h->n_inst), dim3(64), 0, h->stream,
                        reinterpret_cast<const InstDev *>(ws + h->off_inst * 4),
                        reinterpret_cast<const TableDev *>(ws + h->off_tabs * 4),
                        reinterpret_cast<const uint32_t *>(ws), h->buf.perm, h->buf.energy,
-                       h->buf.swap_acc, h->buf.t, 0, 1, 0);
+                       h->buf.swap_acc, h->buf.t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "pt_swap: launch");
     return HS_OK;

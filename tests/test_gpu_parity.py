@@ -218,19 +218,22 @@ def test_hardness_eval_matches_oracle():
         assert (ln[n] == o["ln_tts"]) or (np.isinf(ln[n]) and np.isinf(o["ln_tts"]))
 
 
-def test_full_size_c8_batch_sampled():
-    """The 256-instance C8 batch in the benchmark's launch configuration:
-    sampled instances re-run one by one on the oracle match bit-exactly, and
-    every instance's incremental energies equal the recomputed ones."""
+@pytest.mark.parametrize("swap_interval", [1, 10])
+def test_full_size_c8_batch_sampled(swap_interval):
+    """The 256-instance C8 batch in the benchmark's launch configuration
+    (exchange every sweep, and every 10th sweep as in the elementary Monte
+    Carlo step): sampled instances re-run one by one on the oracle match
+    bit-exactly, and every instance's incremental energies equal the
+    recomputed ones."""
     hs = _gpu()
     cfg = workloads.batch_c8()
     insts = workloads.make_batch(cfg)
-    b = hs.PTBatch(insts, cfg["seed"], swap_interval=cfg["swap_interval"])
+    b = hs.PTBatch(insts, cfg["seed"], swap_interval=swap_interval)
     n_sweeps = 150
     b.sweep(n_sweeps)
     assert b.measure() == 0
     for n in (0, 137, 255):
-        _say(f"C8 full-batch parity: instance {n}")
-        o = _oracle_run(insts[n], cfg["seed"], cfg["swap_interval"], n_sweeps)
+        _say(f"C8 full-batch parity (swap_interval {swap_interval}): instance {n}")
+        o = _oracle_run(insts[n], cfg["seed"], swap_interval, n_sweeps)
         _assert_same(b.state(n), o, f"instance {n}")
     b.close()

@@ -84,11 +84,11 @@ def parity_c4():
 
 
 def batch_c8():
-    """256 C8 instances, J in {+-1..+-7}, K = 32 (beta 0.1..5.0) x R = 2, 10^5 sweeps.
-    Exchange sweep every 10 Metropolis sweeps (the elementary Monte Carlo step of
-    Sec. III.B)."""
+    """256 C8 instances, J in {+-1..+-7}, K = 32 (beta 0.1..5.0) x R = 2, 10^5 sweeps,
+    an exchange pass after every sweep.  (The elementary Monte Carlo step of
+    Sec. III.B, 10 sweeps per exchange pass, is swap_interval = 10.)"""
     return dict(name="C8 x256, K32 R2, +-7", L=8, alphabet="pm7", seed=1605, n_inst=256,
-                K=32, R=2, beta=(0.1, 5.0), sweeps=100_000, swap_interval=10, missing=0.0)
+                K=32, R=2, beta=(0.1, 5.0), sweeps=100_000, swap_interval=1, missing=0.0)
 
 
 def uneven_batch(n_inst=1024, seed=1606):
@@ -104,7 +104,7 @@ def uneven_batch(n_inst=1024, seed=1606):
                           K=int(Ks[n]), R=1, beta=geometric_betas(0.1, 5.0, int(Ks[n])),
                           instance_id=n))
     return dict(name=f"uneven x{n_inst}, C4..C12, 2% missing, K24..48 R1, +-3",
-                seed=seed, sweeps=100_000, swap_interval=10, instances=insts)
+                seed=seed, sweeps=100_000, swap_interval=1, instances=insts)
 
 
 def make_batch(cfg, n_inst=None):
