@@ -234,6 +234,7 @@ void build_tables(int K, const double *beta, HostTables &t)
         }
         t.ts_dmax[k] = int32_t(d - 1);
     }
+    t.ts_hi.push_back(0);                          // a clamped read of an empty last row stays inside
     if (t.ts_hi.size() % 2) t.ts_hi.push_back(0);  // keep uint32 alignment
 }
 

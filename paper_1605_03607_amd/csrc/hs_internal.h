@@ -37,6 +37,10 @@ struct alignas(16) InstDev {
     int32_t n_live_edges, task_iters;  // task_iters: pair iterations per wavefront and phase
     int64_t task_off;   // uint32 offset of the wavefront task table of this lattice size
     int64_t cost;       // sweeps x cells, used to order the work queue
+    int32_t tri;        // (K - 1) K / 2: exchange tests (start j <= pair k) per replica set
+    uint32_t tri_m;     // ceil(2^32 / tri) for tri >= 2: q / tri = mul_hi(q, tri_m) for q < 2^12
+    uint32_t k_m;       // ceil(2^16 / K): l / K = (l k_m) >> 16 for l < 64
+    int32_t pad_;
 };
 
 // Metropolis and exchange tables of one temperature ladder.

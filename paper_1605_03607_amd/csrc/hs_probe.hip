@@ -120,14 +120,14 @@ extern "C" int hs_probe_rate(int which, int iters, double *ops_per_s, void *scra
         }
     };
     launch(1);
-    hipEventRecord(a, nullptr);
+    (void)hipEventRecord(a, nullptr);
     launch(iters);
-    hipEventRecord(b, nullptr);
+    (void)hipEventRecord(b, nullptr);
     if (hipEventSynchronize(b) != hipSuccess) return -4;
     float ms = 0.f;
-    hipEventElapsedTime(&ms, a, b);
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     const double ops = double(blocks) * threads * iters * kUnroll * kChains;
     *ops_per_s = ops / (double(ms) * 1e-3);
     return 0;

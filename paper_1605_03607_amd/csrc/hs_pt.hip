@@ -192,10 +192,10 @@ __device__ __forceinline__ int wave_min(int v)
 // ---------------------------------------------------------------------------
 // Dynamic LDS layout of the sweep kernel.
 struct LdsLayout {
-    uint32_t S, ths, tshi, Eacc, perm, slot, sacc, xrow, stopv, misc, total;
+    uint32_t S, ths, tshi, Eacc, perm, slot, sacc, ux, xrow, stopv, misc, total;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max)
+__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int r_max)
 {
     LdsLayout l;
     uint32_t o = 0;
@@ -213,10 +213,12 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max)
     o += 64 * 4;
     l.sacc = o;
     o += 64 * 4;
+    l.ux = o;
+    o += 64 * 4;                                  // uniforms of the exchange pass, pair r (K-1) + k
     l.xrow = o;
-    o += 4 * 64 * 4;                              // exchange-table rows of pair (k, k+1), k = index
+    o += 2 * 64 * 4;                              // exchange-table row start and length of pair (k, k+1)
     l.stopv = o;
-    o += 64 * 64;                                 // run ends of the exchange pass, [set][start]
+    o += uint32_t(r_max) * 64 * 4;                // run ends of the exchange pass, [set][start]
     l.misc = o;
     o += 16 * 4;
     l.total = o;
@@ -241,32 +243,41 @@ struct SweepArgs {
     int32_t swap_interval;
     int64_t n_sweeps;
     uint32_t flags;
-    int32_t ncell_max, tshi_max;
+    int32_t ncell_max, tshi_max, r_max;
     int32_t lds_ts_ok;        // 1 if every ladder's fast exchange table fits in LDS
 };
 
-// Exchange decision (detailed balance, Sec. II) for configuration x at slot k
-// and y at slot k + 1: d = E_x - E_y, accept iff d <= 0 or
-// u < floor(2^32 exp(-(beta_{k+1} - beta_k) d)).  The 16-bit table decides
-// unless the high halves tie; then the exact 32-bit table does.
-__device__ __forceinline__ bool swap_accept(int d, uint32_t u, int row, int dhi, int dmx, int frow,
-                                            const TableDev &tb, const uint32_t *ws32,
-                                            const uint16_t *tshi_lds, bool use_lds)
+// Exchange decisions (detailed balance, Sec. II) for configuration x at
+// slot k and y at slot k + 1: d = E_x - E_y, accept iff d <= 0 or
+// u < floor(2^32 exp(-(beta_{k+1} - beta_k) d)).  A 16-bit table (the high
+// halves of the thresholds for d = 1..dhi(k)) decides unless the high halves
+// tie; ties are settled with the exact 32-bit table.
+
+// The uniforms of one exchange pass: lane p < (K-1) R gets word 0 of
+// Philox(key, (t, k, r, use)) for pair p = r (K-1) + k.
+__device__ __forceinline__ uint32_t exchange_uniform(uint32_t t, uint32_t use, int K, int R, uint32_t key0,
+                                                     uint32_t key1)
 {
-    if (d <= 0) return true;
-    uint32_t th = 0;
-    if (d <= dhi) {
-        const int at = row + d - 1;
-        th = use_lds ? tshi_lds[at] : reinterpret_cast<const uint16_t *>(ws32 + tb.ts_hi_off)[at];
-    }
-    const uint32_t u16 = u >> 16;
-    if (u16 != th) return u16 < th;
-    const uint32_t tf = d <= dmx ? ws32[tb.ts_full_off + frow + d - 1] : 0u;
-    return u < tf;
+    const int lane = threadIdx.x & 63;
+    const int km1 = max(K - 1, 1);
+    const int r = lane / km1, k = lane - r * km1;
+    const uint32_t u = philox(t, uint32_t(k), uint32_t(r), use, key0, key1).x;
+    return lane < (K - 1) * R ? u : 0u;
 }
 
-// Exchange-table rows of pair (k, k + 1) for k = 0..K-2: xrow[0..3][k] =
-// start of the 16-bit row, its length, length of the exact row, its start.
+// An exchange pass is one ascending sweep over the pairs (k, k+1) of each
+// replica set.  The configuration at slot k when pair k is tested is the one
+// that started at the beginning j of the current run of accepted exchanges
+// (a rejection at k starts a new run at k + 1).
+//
+// Step 1 (every wavefront): for each set r and start j, stop(j) = the first
+// pair k >= j rejected when slot k holds the configuration from slot j
+// (K - 1 if none).  The R (K-1) K / 2 tests (r, j <= k) are spread one per
+// lane over the workgroup, q = r T + k (k + 1) / 2 + j, and rejections are
+// merged into stopv[r][j] (K - 1 beforehand) with an LDS atomic minimum.
+
+// Row start and 16-bit row length of the exchange table of pair (k, k + 1),
+// k = i < K - 1 (xrow[i], xrow[64 + i]).
 __device__ __forceinline__ void load_xrows(int32_t *xrow, const TableDev &tb, const uint32_t *ws32, int K,
                                            int i)
 {
@@ -274,74 +285,95 @@ __device__ __forceinline__ void load_xrows(int32_t *xrow, const TableDev &tb, co
         const bool ok = i < K - 1;
         xrow[i] = ok ? int32_t(ws32[tb.ts_row_off + i]) : 0;
         xrow[64 + i] = ok ? int32_t(ws32[tb.ts_dhi_off + i]) : 0;
-        xrow[128 + i] = ok ? int32_t(ws32[tb.ts_dmax_off + i]) : 0;
-        xrow[192 + i] = ok ? int32_t(ws32[tb.ts_full_row_off + i]) : 0;
     }
 }
 
-// An exchange pass is one ascending sweep over the pairs (k, k+1) of each
-// replica set.  The configuration at slot k when pair k is tested is the one
-// that started at the beginning j of the current run of accepted exchanges
-// (a rejection at k starts a new run at k + 1).  Step 1: for every set r and
-// every possible start j, stop(j) = the first pair k >= j rejected when slot
-// k holds the configuration from slot j (K - 1 if none).  All wavefronts
-// share the (K-1) R tests; one lane per pair k, one pass per (r, j).
-__device__ void exchange_stops(uint32_t t, uint32_t use, int K, int R, uint32_t key0, uint32_t key1,
-                               int wave, int nwaves, const int32_t *E, const int32_t *perm,
-                               const int32_t *xrow, uint8_t *stopv, const TableDev &tb,
-                               const uint32_t *ws32, const uint16_t *tshi, bool use_lds)
+template <bool kLds>
+__device__ void exchange_stops(int K, int R, int tri, uint32_t tri_m, int wave, int nwaves, const int32_t *E,
+                               const int32_t *perm, const uint32_t *ux, const int32_t *xrow, int32_t *stopv,
+                               const TableDev &tb, const uint32_t *ws32, const uint16_t *tshi)
 {
     const int lane = threadIdx.x & 63;
-    const int npair = (K - 1) * R;
-    if (wave >= npair) return;
-    // uniform of pair (k, r) in lane k R + r
-    uint32_t udraw = 0;
-    if (lane < npair) udraw = philox(t, uint32_t(lane / R), uint32_t(lane % R), use, key0, key1).x;
-    const int row = xrow[lane], dhi = xrow[64 + lane], dmx = xrow[128 + lane], frow = xrow[192 + lane];
-    for (int P = wave; P < npair; P += nwaves) {
-        const int r = P % R, j = P / R;
-        const bool valid = lane >= j && lane <= K - 2;
-        const int kc = valid ? lane : j;
-        const int x = perm[j * R + r];
-        const int y = perm[(kc + 1) * R + r];
-        const uint32_t u = __shfl(udraw, kc * R + r, 64);
-        bool rej = false;
-        if (valid) rej = !swap_accept(E[x] - E[y], u, row, dhi, dmx, frow, tb, ws32, tshi, use_lds);
-        const uint64_t m = __ballot(rej);
-        if (lane == 0) stopv[r * 64 + j] = uint8_t(m ? __ffsll((unsigned long long)m) - 1 : K - 1);
+    const int ntest = tri * R;
+    if (wave * 64 >= ntest) return;
+    // per-lane values, gathered by the tests with bpermute
+    const int es = E[perm[lane] & 63];  // energy of the configuration at slot index k R + r
+    const uint32_t uxv = ux[lane];      // uniform of pair r (K-1) + k
+    const int rowv = xrow[lane], dhiv = xrow[64 + lane];
+    const uint16_t *ghi = reinterpret_cast<const uint16_t *>(ws32 + tb.ts_hi_off);
+    for (int base = wave * 64; base < ntest; base += nwaves * 64) {
+        const int q = min(base + lane, ntest - 1);
+        const int r = tri == 1 ? q : int(__umulhi(uint32_t(q), tri_m));
+        const int rem = q - r * tri;
+        int k = int((__fsqrt_rn(float(8 * rem + 1)) - 1.0f) * 0.5f);
+        k += ((k + 1) * (k + 2) / 2 <= rem) ? 1 : 0;
+        k -= (k * (k + 1) / 2 > rem) ? 1 : 0;
+        const int j = rem - k * (k + 1) / 2;
+        const int ex = __shfl(es, j * R + r, 64);
+        const int ey = __shfl(es, (k + 1) * R + r, 64);
+        const uint32_t u = __shfl(uxv, r * (K - 1) + k, 64);
+        const int row = __shfl(rowv, k, 64), dh = __shfl(dhiv, k, 64);
+        const int d = ex - ey;
+        const int at = row + min(max(d, 1), max(dh, 1)) - 1;  // clamped into the row
+        uint32_t h;
+        if constexpr (kLds)
+            h = tshi[at];
+        else
+            h = ghi[at];
+        const uint32_t th = d <= dh ? h : 0u;
+        const uint32_t u16 = u >> 16;
+        bool rej = d > 0 && u16 > th;
+        const bool tie = d > 0 && u16 == th;
+        if (__any(tie)) {  // rare: exact table
+            if (tie) {
+                const int dmx = int(ws32[tb.ts_dmax_off + k]);
+                const uint32_t tf = d <= dmx ? ws32[tb.ts_full_off + ws32[tb.ts_full_row_off + k] + d - 1] : 0u;
+                rej = !(u < tf);
+            }
+        }
+        if (rej && base + lane < ntest) atomicMin(&stopv[r * 64 + j], k);
     }
 }
 
-// Step 2 (wavefront w takes the sets r = w, w + nwaves, ...): follow the run
-// starts 0, stop(0) + 1, ... and apply the pass.  Slot k of a run that starts
-// at j receives the configuration from slot k + 1 if k < stop(j) (accepted)
-// and the carried configuration from slot j if k = stop(j).
-__device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm, int32_t *slot,
-                               uint32_t *sacc, const uint8_t *stopv)
+// Step 2 (one wavefront, lane l = r K + j): follow the run starts 0,
+// stop(0) + 1, ... of every set by binary lifting: jump tables
+// next^(2^m)(j) with next(j) = stop(j) + 1 (K = past the end), then every
+// slot k finds the last run start <= k.  Slot k of a run that starts at j
+// receives the configuration from slot k + 1 if k < stop(j) (accepted) and
+// the carried configuration from slot j if k = stop(j).
+__device__ void exchange_apply(int K, int R, uint32_t k_m, int32_t *perm, int32_t *slot, uint32_t *sacc,
+                               int32_t *stopv)
 {
     const int lane = threadIdx.x & 63;
-    for (int r = wave; r < R; r += nwaves) {
-        const int sv = lane < K - 1 ? int(stopv[r * 64 + lane]) : K - 1;
-        uint64_t starts = 0;
-        int s = 0;
-        for (;;) {
-            starts |= 1ull << s;
-            if (s >= K - 1) break;
-            const int nx = __builtin_amdgcn_readlane(sv, s) + 1;
-            if (nx > K - 1) break;
-            s = nx;
-        }
-        const uint64_t below = lane == 63 ? starts : (starts & ((2ull << lane) - 1ull));
-        const int jk = 63 - __clzll((long long)below);  // start of the run holding slot `lane`
-        const int st = __shfl(sv, jk, 64);
-        const int oj = perm[jk * R + r];
-        const int on = perm[min(lane + 1, K - 1) * R + r];
-        const int np = lane == st ? oj : on;
-        if (lane < K) {
-            perm[lane * R + r] = np;
-            slot[np] = lane | (r << 8);
-            if (lane < K - 1 && lane != st) sacc[lane * R + r] += 1u;
-        }
+    const int r = int((uint32_t(lane) * k_m) >> 16);  // lane / K
+    const int j = lane - r * K;
+    const bool valid = lane < K * R;
+    const int base = r * K;
+    int J[6];
+    J[0] = K;
+    if (valid && j < K - 1) {
+        J[0] = stopv[r * 64 + j] + 1;
+        stopv[r * 64 + j] = K - 1;  // ready for the next pass
+    }
+#pragma unroll
+    for (int m = 1; m < 6; ++m) {
+        const int y = __shfl(J[m - 1], base + min(J[m - 1], K - 1), 64);
+        J[m] = J[m - 1] >= K ? K : y;
+    }
+    int x = 0;
+#pragma unroll
+    for (int m = 5; m >= 0; --m) {
+        const int y = __shfl(J[m], base + x, 64);
+        x = y <= j ? y : x;
+    }
+    const int st = __shfl(J[0], base + x, 64) - 1;  // stop of the run holding slot j
+    if (valid) {
+        const int oj = perm[x * R + r];
+        const int on = perm[min(j + 1, K - 1) * R + r];
+        const int np = j == st ? oj : on;
+        perm[j * R + r] = np;
+        slot[np] = j | (r << 8);
+        if (j < K - 1 && j != st) sacc[j * R + r] += 1u;
     }
 }
 
@@ -426,7 +458,7 @@ __device__ __forceinline__ int site_m4(uint32_t own, uint32_t oth, uint32_t xv, 
 __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
 {
     extern __shared__ __align__(16) char lds[];
-    const LdsLayout L = lds_layout(a.ncell_max, a.tshi_max);
+    const LdsLayout L = lds_layout(a.ncell_max, a.tshi_max, a.r_max);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -437,8 +469,9 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
     int32_t *perm = reinterpret_cast<int32_t *>(lds + L.perm);
     int32_t *slot = reinterpret_cast<int32_t *>(lds + L.slot);
     uint32_t *sacc = reinterpret_cast<uint32_t *>(lds + L.sacc);
+    uint32_t *ux = reinterpret_cast<uint32_t *>(lds + L.ux);
     int32_t *xrow = reinterpret_cast<int32_t *>(lds + L.xrow);
-    uint8_t *stopv = reinterpret_cast<uint8_t *>(lds + L.stopv);
+    int32_t *stopv = reinterpret_cast<int32_t *>(lds + L.stopv);
     int32_t *misc = reinterpret_cast<int32_t *>(lds + L.misc);
     uint16_t *tshi = reinterpret_cast<uint16_t *>(lds + L.tshi);
     const bool stop_mode = (a.flags & HS_STOP_ON_AGREEMENT) != 0;
@@ -484,6 +517,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             uint32_t *dst = reinterpret_cast<uint32_t *>(tshi);
             for (int i = tid; i < (tb.lds_ts_entries + 1) / 2; i += blockDim.x) dst[i] = src[i];
         }
+        for (int i = tid; i < R * 64; i += blockDim.x) stopv[i] = K - 1;
         load_xrows(xrow, tb, a.ws32, K, tid);
         if (tid < 64) {
             slot[tid] = 0;
@@ -521,6 +555,8 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         const cptr<uint32_t> task = ws4 + d.task_off;
         const uint32_t s_base = L.S + uint32_t(lane) * 4u;
         const RoundKeys RK = round_keys(key0, key1);
+        const int tri = d.tri;
+        const uint32_t tri_m = d.tri_m, k_m = d.k_m;
 
         for (int64_t sw = 0; sw < a.n_sweeps && !stopped; ++sw) {
             const uint32_t tt = uint32_t(t);
@@ -636,6 +672,8 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     if (second) *reinterpret_cast<uint32_t *>(lds + orow[1]) = nw[1];
                 }
                 if (p == 1 && live) atomicAdd(&Eb[lane], (e4 + int(nrej >> 3)) >> 2);
+                // the uniforms of a due exchange pass, drawn by the last wavefront
+                if (p == 1 && cd == 0 && wave == nwaves - 1) ux[lane] = exchange_uniform(tt, kUseSwap, K, R, key0, key1);
                 __syncthreads();
             }
             // ---- lane energies, running minima, agreement, exchange ----
@@ -660,10 +698,14 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             }
             const bool stop_now = stop_mode && agree && (t + 1) >= 2 * tmax;
             if (cd == 0) {
-                exchange_stops(tt, kUseSwap, K, R, key0, key1, wave, nwaves, Eb, perm, xrow, stopv, tb,
-                               a.ws32, tshi, a.lds_ts_ok != 0);
+                if (a.lds_ts_ok)
+                    exchange_stops<true>(K, R, tri, tri_m, wave, nwaves, Eb, perm, ux, xrow, stopv, tb, a.ws32,
+                                         tshi);
+                else
+                    exchange_stops<false>(K, R, tri, tri_m, wave, nwaves, Eb, perm, ux, xrow, stopv, tb, a.ws32,
+                                          tshi);
                 __syncthreads();
-                exchange_apply(K, R, wave, nwaves, perm, slot, sacc, stopv);
+                if (wave == 0) exchange_apply(K, R, k_m, perm, slot, sacc, stopv);
                 __syncthreads();
             }
             if (si > 0) cd = cd == 0 ? si - 1 : cd - 1;
@@ -798,9 +840,8 @@ __global__ void __launch_bounds__(64) k_swap_extra(const InstDev *inst, const Ta
                                                    const int32_t *energy, uint32_t *swap_acc,
                                                    const int64_t *t)
 {
-    __shared__ int32_t E[64], perm[64], slot[64], xrow[256];
-    __shared__ uint32_t sacc[64];
-    __shared__ uint8_t stopv[64 * 64];
+    __shared__ int32_t E[64], perm[64], slot[64], xrow[128], stopv[64 * 64];
+    __shared__ uint32_t sacc[64], ux[64];
     const int n = blockIdx.x, lane = threadIdx.x;
     const InstDev d = inst[n];
     const TableDev tb = tabs[d.tab];
@@ -808,12 +849,13 @@ __global__ void __launch_bounds__(64) k_swap_extra(const InstDev *inst, const Ta
     perm[lane] = perm_g[n * 64 + lane];
     sacc[lane] = swap_acc[n * 64 + lane];
     slot[lane] = 0;
+    for (int i = lane; i < d.R * 64; i += 64) stopv[i] = d.K - 1;
     load_xrows(xrow, tb, ws32, d.K, lane);
+    ux[lane] = exchange_uniform(uint32_t(t[n]), kUseSwapExtra, d.K, d.R, d.key0, d.key1);
     __syncthreads();
-    exchange_stops(uint32_t(t[n]), kUseSwapExtra, d.K, d.R, d.key0, d.key1, 0, 1, E, perm, xrow, stopv, tb,
-                   ws32, nullptr, false);
+    exchange_stops<false>(d.K, d.R, d.tri, d.tri_m, 0, 1, E, perm, ux, xrow, stopv, tb, ws32, nullptr);
     __syncthreads();
-    exchange_apply(d.K, d.R, 0, 1, perm, slot, sacc, stopv);
+    exchange_apply(d.K, d.R, d.k_m, perm, slot, sacc, stopv);
     __syncthreads();
     perm_g[n * 64 + lane] = uint8_t(perm[lane]);
     swap_acc[n * 64 + lane] = sacc[lane];
@@ -834,7 +876,7 @@ struct hs_pt {
     int32_t swap_interval = 0;
     int nwaves = 16;
     int grid = 0;
-    int ncell_max = 0, tshi_max = 0;
+    int ncell_max = 0, tshi_max = 0, r_max = 1;
     int lds_ts_ok = 1;
     size_t lds_bytes = 0;
     // workspace layout (byte offsets)
@@ -857,7 +899,7 @@ struct Plan {
     std::vector<uint32_t> image;  // workspace image in uint32 words
     int nwaves = 16;
     size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0;
-    int ncell_max = 0, K_max = 0, tshi_max = 0;
+    int ncell_max = 0, K_max = 0, tshi_max = 0, r_max = 1;
     int lds_ts_ok = 1;
     size_t total_words = 0;
 };
@@ -944,6 +986,7 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
         P.tab_of[i] = found;
         P.ncell_max = std::max(P.ncell_max, P.hi[i].ncell);
         P.K_max = std::max(P.K_max, in.K);
+        P.r_max = std::max(P.r_max, in.R);
     }
     // wavefronts per workgroup: one per cell pair of the largest instance, up to 16
     if (d.block_waves > 0) {
@@ -1000,6 +1043,9 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
         x.task_off = task_off[in.L];
         x.task_iters = task_iters[in.L];
         x.cost = int64_t(x.ncell);
+        x.tri = (in.K - 1) * in.K / 2;
+        x.tri_m = x.tri > 1 ? uint32_t(((uint64_t(1) << 32) + uint64_t(x.tri) - 1) / uint64_t(x.tri)) : 0u;
+        x.k_m = uint32_t((65536 + in.K - 1) / in.K);
     }
     for (size_t t = 0; t < P.ht.size(); ++t) {
         const HostTables &h = P.ht[t];
@@ -1018,11 +1064,11 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
         P.tshi_max = std::max(P.tshi_max, int(h.ts_hi.size()));
     }
     if (size_t(P.tshi_max) * 2 > kLdsTsBudget ||
-        dev::lds_layout(P.ncell_max, P.tshi_max).total > kLdsLimit) {
+        dev::lds_layout(P.ncell_max, P.tshi_max, P.r_max).total > kLdsLimit) {
         P.lds_ts_ok = 0;
         P.tshi_max = 0;
     }
-    if (dev::lds_layout(P.ncell_max, 0).total > kLdsLimit) {
+    if (dev::lds_layout(P.ncell_max, 0, P.r_max).total > kLdsLimit) {
         err = "instance too large for one workgroup's LDS";
         return HS_EUNSUPPORTED;
     }
@@ -1100,12 +1146,13 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
     h->nwaves = P.nwaves;
     h->ncell_max = P.ncell_max;
     h->tshi_max = P.tshi_max;
+    h->r_max = P.r_max;
     h->lds_ts_ok = P.lds_ts_ok;
     h->off_inst = P.off_inst;
     h->off_tabs = P.off_tabs;
     h->off_order = P.off_order;
     h->off_queue = P.off_queue;
-    h->lds_bytes = dev::lds_layout(h->ncell_max, h->tshi_max).total;
+    h->lds_bytes = dev::lds_layout(h->ncell_max, h->tshi_max, h->r_max).total;
     h->host_ws = std::move(P.image);
     if (h->n_inst == 0) {
         *out = h;
@@ -1180,6 +1227,7 @@ int pt_sweep(hs_pt *h, int64_t n_sweeps)
     a.flags = h->flags;
     a.ncell_max = h->ncell_max;
     a.tshi_max = h->tshi_max;
+    a.r_max = h->r_max;
     a.lds_ts_ok = h->lds_ts_ok;
     hipLaunchKernelGGL(dev::k_reset_queue, dim3(1), dim3(1), 0, h->stream, a.queue);
     hipLaunchKernelGGL(dev::k_pt_sweep, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, h->stream, a);
