@@ -15,9 +15,10 @@
 //     halves come from a second Philox use and are computed only when a lane
 //     ties on the high half (probability 2^-16 per attempt).
 //   * Thresholds: fast table thi[k][m] = T >> 16 (0x10000 for m <= 0), held
-//     in LDS as one column per slot index k R + r.  The slot indices of the
-//     64 lanes are a permutation, so the per-lane gather is free of bank
-//     conflicts and the table never changes.  The exact table
+//     in LDS as one column per slot (k, r), column r K + k.  A lane's column
+//     moves with its slot; the columns of the 64 lanes are a permutation that
+//     keeps each replica set in its own block, so the per-lane gather is free
+//     of bank conflicts and the table never changes.  The exact table
 //     T = floor(2^32 exp(-2 beta m)) stays in global memory for ties.
 //   * Exchange passes: every wavefront evaluates part of the acceptance tests
 //     of pair (k, k+1) for every configuration that can be carried into slot
@@ -506,10 +507,12 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             S[q * 64 + lane] = w;
         }
         if (wave == 0) S[ncell * 2 * 64 + lane] = 0u;  // zero row for absent neighbours
-        // threshold column of slot index k R + r holds the row of temperature k
+        // threshold column r K + k holds the row of temperature k: the lanes of
+        // a replica set occupy one block of columns, so each half-wavefront
+        // gathers from distinct banks
         for (int i = tid; i < kMRow * 64; i += blockDim.x) {
             const int m = i >> 6, sx = i & 63;
-            const int k = sx < nlanes ? sx / R : 0;
+            const int k = sx < nlanes ? sx % K : 0;
             THS[i] = a.ws32[tb.thi_off + k * kMRow + m];
         }
         if (a.lds_ts_ok) {
@@ -552,6 +555,8 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         int cd = si > 0 ? int((int64_t(si) - (t + 1) % si) % si) : -1;
         const int npairs = d.npairs;
         const int iters = d.task_iters;
+        // pair tasks of this wavefront per phase: it = 0 .. nt-1 with wave + it nwaves < npairs
+        const int nt = wave < npairs ? min(iters, (npairs - wave + nwaves - 1) / nwaves) : 0;
         const cptr<uint32_t> task = ws4 + d.task_off;
         const uint32_t s_base = L.S + uint32_t(lane) * 4u;
         const RoundKeys RK = round_keys(key0, key1);
@@ -563,7 +568,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             // per-lane slot state (changes only in exchange passes)
             const int sl = slot[lane];
             const int kslot = min(sl & 0xFF, K - 1);
-            const uint32_t sidx = live ? uint32_t(kslot * R + (sl >> 8)) : uint32_t(lane);
+            const uint32_t sidx = live ? uint32_t((sl >> 8) * K + kslot) : uint32_t(lane);
             const uint32_t sword = (uint32_t(sl & 0xFF) << 8) | uint32_t(sl >> 8);
             // threshold column of this lane's slot, entry m at byte m * 256
             const uint32_t thl_base = L.ths + uint32_t(kMaxM) * 256u + sidx * 4u;
@@ -580,37 +585,49 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             int e4 = 0;        // phase 1: sum of (m4 ^ s) over this wavefront's sites
             uint32_t nrej = 0; // phase 1: 8 x rejected sites
 
+            // The Philox draw of the next task (the next pair of this phase, or
+            // the first pair of phase 1) is computed while the spin rows of the
+            // current task are being read.
+            uint4 rw_next = make_uint4(0u, 0u, 0u, 0u);
+            if (nt > 0) rw_next = metro_call(ml, mu, task[(wave * 2) * iters * 8], RK);
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                for (int it = 0; it < iters; ++it) {
-                    if (wave + it * nwaves >= npairs) break;
+                for (int it = 0; it < nt; ++it) {
                     // task entry: counter word, quad indices, spin rows (scalar loads)
                     const cptr<uint32_t> te = task + ((wave * 2 + p) * iters + it) * 8;
                     const uint32_t c1 = te[0];
                     const uint32_t qq = te[1];
                     const bool second = (qq >> 16) != 0xFFFFu;
-                    const uint4 rw = metro_call(ml, mu, c1, RK);
-                    uint32_t own[2], nw[2], orow[2];
+                    uint32_t orow[2], o0[2], oth[2], A[2], B[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t roo = te[2 + 2 * h], rab = te[3 + 2 * h];
+                        orow[h] = s_base + ((roo & 0xFFFFu) << 8);
+                        o0[h] = *reinterpret_cast<const uint32_t *>(lds + orow[h]);
+                        oth[h] = *reinterpret_cast<const uint32_t *>(lds + s_base + ((roo >> 16) << 8));
+                        A[h] = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab & 0xFFFFu) << 8));
+                        B[h] = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab >> 16) << 8));
+                    }
+                    const uint4 rw = rw_next;
+                    if (it + 1 < nt || p == 0) {
+                        const uint32_t c1n = it + 1 < nt ? te[8] : task[((wave * 2 + 1) * iters) * 8];
+                        rw_next = metro_call(ml, mu, c1n, RK);
+                    }
+                    uint32_t nw[2];
                     const int e4_save = e4;
                     const uint32_t nrej_save = nrej;
                     uint32_t tmin = 0xFFFFFFFFu;
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const uint32_t roo = te[2 + 2 * h], rab = te[3 + 2 * h];
                         const uint32_t q = (h == 0 || !second) ? (qq & 0xFFFFu) : (qq >> 16);
                         const cptr<uint32_t> jq = jw + q * 8;
                         const uint32_t fm = livew[q];
-                        orow[h] = s_base + ((roo & 0xFFFFu) << 8);
-                        const uint32_t o0 = *reinterpret_cast<const uint32_t *>(lds + orow[h]);
-                        const uint32_t oth = *reinterpret_cast<const uint32_t *>(lds + s_base + ((roo >> 16) << 8));
-                        const uint32_t A = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab & 0xFFFFu) << 8));
-                        const uint32_t B = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab >> 16) << 8));
-                        const uint32_t x01 = __builtin_amdgcn_perm(B, A, 0x05040100u);
-                        const uint32_t x23 = __builtin_amdgcn_perm(B, A, 0x07060302u);
-                        const int m0 = site_m4<0>(o0, oth, x01, jq[0], jq[4]);
-                        const int m1 = site_m4<1>(o0, oth, x01, jq[1], jq[5]);
-                        const int m2 = site_m4<2>(o0, oth, x23, jq[2], jq[6]);
-                        const int m3 = site_m4<3>(o0, oth, x23, jq[3], jq[7]);
+                        const uint32_t x01 = __builtin_amdgcn_perm(B[h], A[h], 0x05040100u);
+                        const uint32_t x23 = __builtin_amdgcn_perm(B[h], A[h], 0x07060302u);
+                        const int m0 = site_m4<0>(o0[h], oth[h], x01, jq[0], jq[4]);
+                        const int m1 = site_m4<1>(o0[h], oth[h], x01, jq[1], jq[5]);
+                        const int m2 = site_m4<2>(o0[h], oth[h], x23, jq[2], jq[6]);
+                        const int m3 = site_m4<3>(o0[h], oth[h], x23, jq[3], jq[7]);
                         const uint32_t t0 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m0 * 64);
                         const uint32_t t1 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m1 * 64);
                         const uint32_t t2 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m2 * 64);
@@ -631,8 +648,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                             e4 += (m0 ^ s0) + (m1 ^ s1) + (m2 ^ s2) + (m3 ^ s3);
                             nrej += __builtin_popcount(rej);
                         }
-                        own[h] = o0;
-                        nw[h] = o0 ^ (~rej & fm);
+                        nw[h] = o0[h] ^ (~rej & fm);
                     }
                     if (__any(tmin == 0u)) {
                         // exact pass for this pair: full 32-bit uniforms
@@ -642,20 +658,15 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         e4 = e4_save;
                         nrej = nrej_save;
                         for (int h = 0; h < 2; ++h) {
-                            const uint32_t roo = te[2 + 2 * h], rab = te[3 + 2 * h];
                             const uint32_t q = (h == 0 || !second) ? (qq & 0xFFFFu) : (qq >> 16);
                             const cptr<uint32_t> jq = jw + q * 8;
-                            const uint32_t oth = *reinterpret_cast<const uint32_t *>(lds + s_base + ((roo >> 16) << 8));
-                            const uint32_t A = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab & 0xFFFFu) << 8));
-                            const uint32_t B = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab >> 16) << 8));
-                            const uint32_t x01 = __builtin_amdgcn_perm(B, A, 0x05040100u);
-                            const uint32_t x23 = __builtin_amdgcn_perm(B, A, 0x07060302u);
-                            const uint32_t o0 = own[h];
+                            const uint32_t x01 = __builtin_amdgcn_perm(B[h], A[h], 0x05040100u);
+                            const uint32_t x23 = __builtin_amdgcn_perm(B[h], A[h], 0x07060302u);
                             int m[4];
-                            m[0] = site_m4<0>(o0, oth, x01, jq[0], jq[4]);
-                            m[1] = site_m4<1>(o0, oth, x01, jq[1], jq[5]);
-                            m[2] = site_m4<2>(o0, oth, x23, jq[2], jq[6]);
-                            m[3] = site_m4<3>(o0, oth, x23, jq[3], jq[7]);
+                            m[0] = site_m4<0>(o0[h], oth[h], x01, jq[0], jq[4]);
+                            m[1] = site_m4<1>(o0[h], oth[h], x01, jq[1], jq[5]);
+                            m[2] = site_m4<2>(o0[h], oth[h], x23, jq[2], jq[6]);
+                            m[3] = site_m4<3>(o0[h], oth[h], x23, jq[3], jq[7]);
                             uint32_t flip = 0;
                             int ev = 0;
                             for (int k = 0; k < 4; ++k) {
@@ -665,7 +676,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                                 ev += acc ? m[k] : -m[k];
                             }
                             if (p == 1 && (h == 0 || second)) e4 += ev;
-                            nw[h] = o0 ^ (flip & livew[q]);  // flip bytes 0xFE, fm bytes 0xFE
+                            nw[h] = o0[h] ^ (flip & livew[q]);  // flip bytes 0xFE, fm bytes 0xFE
                         }
                     }
                     *reinterpret_cast<uint32_t *>(lds + orow[0]) = nw[0];
