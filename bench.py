@@ -72,6 +72,9 @@ def parse():
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed steps, run one plain device copy of this many MiB "
                         "(reference kernel for scaling HBM byte counters)")
+    p.add_argument("--workload", choices=["c8", "uneven"], default="c8",
+                   help="c8: the 256 x C8 batch (default); uneven: 1024 instances C4..C12, "
+                        "autotuned shape, HIP-graph replay, live attempts/s")
     p.add_argument("--probe", action="store_true",
                    help="also measure instruction issue rates (libhsprobe.so)")
     return p.parse_args()
@@ -116,11 +119,77 @@ def cpu_baseline(cfg, insts, budget_s):
                       f"{el:.1f} s wall"}
 
 
+def uneven(args):
+    """1024 instances of mixed size (C4..C12, 2% missing spins, K 24..48):
+    the workgroup shape chosen by the autotuner, each step one replay of a
+    HIP graph holding the persistent launch.  Counts live attempts only
+    (live sites x K R lanes)."""
+    import torch
+
+    import paper_1605_03607_amd as hs
+    cfg = workloads.uneven_batch()
+    if args.swap_interval is not None:
+        cfg["swap_interval"] = args.swap_interval
+    insts = cfg["instances"]
+    sweeps = args.sweeps or cfg["sweeps"]
+    live_per_sweep = sum(int(d["K"]) * int(d["R"]) * int(np.count_nonzero(d["live"])) for d in insts)
+    lane_slots = sum(64 * 8 * int(d["L"]) ** 2 for d in insts)
+    t0 = time.perf_counter()
+    bw, us = (args.block_waves, None) if args.block_waves else hs.autotune(
+        insts, cfg["seed"], swap_interval=cfg["swap_interval"], trial_sweeps=200)
+    tune_s = time.perf_counter() - t0
+    print(f"# autotune: block_waves={bw} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
+    batch = hs.PTBatch(insts, cfg["seed"], swap_interval=cfg["swap_interval"], block_waves=bw)
+    graph = batch.graph(sweeps)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        graph.launch()
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    mism = batch.measure()
+    attempts = live_per_sweep * sweeps
+    k_avg_s = float(np.mean(kernel_ms)) / 1e3
+    achieved = attempts * A_OPS / k_avg_s
+    out = {
+        "metric": "live spin-flip attempts/s (uneven batch)",
+        "value": attempts * args.steps / wall,
+        "unit": "spin-flip attempts/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": cfg["name"], "instances": len(insts), "sweeps_per_step": sweeps,
+                   "swap_interval": cfg["swap_interval"], "block_waves": bw,
+                   "autotune_us_per_sweep": us, "live_attempts_per_sweep": live_per_sweep,
+                   "live_fraction_of_lane_slots": live_per_sweep / lane_slots},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
+                     "unit": "Tops/s (int32 lane operations)", "frac": achieved / PEAK_INT32_OPS,
+                     "traffic": None, "kernel_ms_avg": float(np.mean(kernel_ms)),
+                     "ops_per_attempt": A_OPS},
+        "energy_mismatches": mism,
+    }
+    graph.close()
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "uneven":
+        uneven(args)
+        return
     import torch
 
     import paper_1605_03607_amd as hs

@@ -142,6 +142,30 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
  * by agreement, Appendix B).  Asynchronous. */
 int pt_sweep(hs_pt *h, int64_t n_sweeps);
 
+/* HIP graph of a sweep launch.  pt_graph_create captures the launches that
+ * pt_sweep(h, n_sweeps) would enqueue (a work-queue reset and one persistent
+ * sweep kernel) on a private capture stream and instantiates them;
+ * pt_graph_launch replays them on h's stream, i.e. enqueues n_sweeps more
+ * sweeps of every instance, exactly as pt_sweep would (the chains continue;
+ * results are identical).  The graph refers to h's buffers: destroy it before
+ * h.  HS_EHIP on a capture or launch failure. */
+typedef struct hs_graph hs_graph;
+int pt_graph_create(hs_pt *h, int64_t n_sweeps, hs_graph **out);
+int pt_graph_launch(hs_graph *g);
+int pt_graph_destroy(hs_graph *g);
+
+/* Workgroup-shape autotuner for a batch (the "tile shape" of a persistent
+ * launch: wavefronts per instance).  For each candidate block_waves in
+ * {2, 4, 8, 16} it initialises the batch on the caller's scratch buffers
+ * (sized as pt_init needs; contents overwritten; candidates whose workspace
+ * does not fit in scratch->workspace_bytes are skipped), runs trial_sweeps / 8
+ * warm-up sweeps and times trial_sweeps sweeps with HIP events on `stream`.
+ * Writes the fastest candidate to *block_waves_out and, if not NULL, its time
+ * per sweep in microseconds.  Synchronises the stream; the trial chains
+ * never touch the caller's real buffers, so tuning does not change results. */
+int pt_autotune(const hs_pt_desc *d, const hs_buffers *scratch, void *stream, int64_t trial_sweeps,
+                int32_t *block_waves_out, double *us_per_sweep_out);
+
 /* Enqueues one extra exchange pass now, outside the sweep schedule, drawing
  * from its own Philox use (counter word 3 = 3) so it never repeats the draws
  * of the scheduled passes.  Asynchronous. */

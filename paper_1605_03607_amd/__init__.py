@@ -81,6 +81,11 @@ def lib():
         L.pt_swap.argtypes = [C.c_void_p]
         L.pt_measure.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
         L.pt_destroy.argtypes = [C.c_void_p]
+        L.pt_graph_create.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_void_p)]
+        L.pt_graph_launch.argtypes = [C.c_void_p]
+        L.pt_graph_destroy.argtypes = [C.c_void_p]
+        L.pt_autotune.argtypes = [C.POINTER(hs_pt_desc), C.POINTER(hs_buffers), C.c_void_p, C.c_int64,
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.instance_mutate.argtypes = [C.POINTER(hs_instance), C.c_void_p, C.c_int, C.c_uint32,
                                       C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(hs_mutation)]
         L.hs_rao_accept.argtypes = [C.c_double, C.c_double, C.c_double, C.c_uint32]
@@ -115,8 +120,9 @@ def probe_rates(iters=2000):
 
 def exported_symbols():
     return ["hs_version", "hs_last_error", "pt_workspace_bytes", "pt_init", "pt_sweep", "pt_swap",
-            "pt_measure", "pt_destroy", "instance_mutate", "hs_rao_accept",
-            "hardness_workspace_bytes", "hardness_eval"]
+            "pt_measure", "pt_destroy", "pt_graph_create", "pt_graph_launch", "pt_graph_destroy",
+            "pt_autotune", "instance_mutate", "hs_rao_accept", "hardness_workspace_bytes",
+            "hardness_eval"]
 
 
 def _check(rc):
@@ -176,25 +182,10 @@ class PTBatch:
                                swap_interval, flags, block_waves)
         nb = C.c_size_t(0)
         _check(lib().pt_workspace_bytes(C.byref(self.desc), C.byref(nb)))
-        dev = torch.device(device)
-        n = max(1, self.n)
-        total = max(1, int(self.offsets[-1]))
-        self.spins = torch.zeros(total, dtype=torch.int64, device=dev)
+        _alloc_buffers(self, torch.device(device), self.n, int(self.offsets[-1]), nb.value)
         if init_spins is not None:
             self.spins.copy_(torch.from_numpy(np.ascontiguousarray(init_spins).view(np.int64)))
-        self.perm = torch.zeros((n, 64), dtype=torch.uint8, device=dev)
-        self.energy = torch.zeros((n, 64), dtype=torch.int32, device=dev)
-        self.emin = torch.zeros((n, 64), dtype=torch.int32, device=dev)
-        self.thit = torch.zeros((n, 64), dtype=torch.int64, device=dev)
-        self.swap_acc = torch.zeros((n, 64), dtype=torch.int32, device=dev)
-        self.t = torch.zeros(n, dtype=torch.int64, device=dev)
-        self.stopped = torch.zeros(n, dtype=torch.int32, device=dev)
-        self.workspace = torch.zeros(max(16, nb.value), dtype=torch.uint8, device=dev)
-        self.recomputed = torch.zeros((n, 64), dtype=torch.int32, device=dev)
-        self.bufs = hs_buffers(self.spins.data_ptr(), self.perm.data_ptr(), self.energy.data_ptr(),
-                               self.emin.data_ptr(), self.thit.data_ptr(), self.swap_acc.data_ptr(),
-                               self.t.data_ptr(), self.stopped.data_ptr(),
-                               self.workspace.data_ptr(), nb.value)
+        self.recomputed = torch.zeros((max(1, self.n), 64), dtype=torch.int32, device=self.spins.device)
         self.stream = stream
         h = C.c_void_p()
         _check(lib().pt_init(C.byref(h), C.byref(self.desc), C.byref(self.bufs),
@@ -203,6 +194,10 @@ class PTBatch:
 
     def sweep(self, n_sweeps):
         _check(lib().pt_sweep(self.h, int(n_sweeps)))
+
+    def graph(self, n_sweeps):
+        """A captured HIP graph whose replay runs n_sweeps more sweeps."""
+        return SweepGraph(self, n_sweeps)
 
     def swap(self):
         _check(lib().pt_swap(self.h))
@@ -243,6 +238,75 @@ class PTBatch:
             self.close()
         except Exception:
             pass
+
+
+class SweepGraph:
+    """pt_graph_create / pt_graph_launch / pt_graph_destroy."""
+
+    def __init__(self, batch, n_sweeps):
+        self.batch = batch
+        g = C.c_void_p()
+        _check(lib().pt_graph_create(batch.h, int(n_sweeps), C.byref(g)))
+        self.g = g
+
+    def launch(self):
+        _check(lib().pt_graph_launch(self.g))
+
+    def close(self):
+        if getattr(self, "g", None):
+            lib().pt_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _alloc_buffers(obj, dev, n_inst, total_spins, workspace_bytes):
+    """Device buffers of a batch (hs_buffers layout) as torch tensors on obj."""
+    torch = _torch()
+    n = max(1, n_inst)
+    obj.spins = torch.zeros(max(1, total_spins), dtype=torch.int64, device=dev)
+    obj.perm = torch.zeros((n, 64), dtype=torch.uint8, device=dev)
+    obj.energy = torch.zeros((n, 64), dtype=torch.int32, device=dev)
+    obj.emin = torch.zeros((n, 64), dtype=torch.int32, device=dev)
+    obj.thit = torch.zeros((n, 64), dtype=torch.int64, device=dev)
+    obj.swap_acc = torch.zeros((n, 64), dtype=torch.int32, device=dev)
+    obj.t = torch.zeros(n, dtype=torch.int64, device=dev)
+    obj.stopped = torch.zeros(n, dtype=torch.int32, device=dev)
+    obj.workspace = torch.zeros(max(16, workspace_bytes), dtype=torch.uint8, device=dev)
+    obj.bufs = hs_buffers(obj.spins.data_ptr(), obj.perm.data_ptr(), obj.energy.data_ptr(),
+                          obj.emin.data_ptr(), obj.thit.data_ptr(), obj.swap_acc.data_ptr(),
+                          obj.t.data_ptr(), obj.stopped.data_ptr(), obj.workspace.data_ptr(),
+                          workspace_bytes)
+
+
+def autotune(insts, seed, swap_interval=1, flags=0, trial_sweeps=200, device="cuda", stream=None):
+    """pt_autotune on scratch buffers: returns (block_waves, microseconds per sweep)."""
+    hi = _HostInstances(insts)
+    desc = hs_pt_desc(len(insts), C.cast(hi.arr, C.POINTER(hs_instance)), seed, swap_interval,
+                      flags, 0)
+    need = 0
+    for bw in (2, 4, 8, 16):
+        desc.block_waves = bw
+        nb = C.c_size_t(0)
+        _check(lib().pt_workspace_bytes(C.byref(desc), C.byref(nb)))
+        need = max(need, nb.value)
+    desc.block_waves = 0
+
+    class _Scratch:
+        pass
+
+    sc = _Scratch()
+    total = sum(8 * int(d["L"]) ** 2 for d in insts)
+    _alloc_buffers(sc, _torch().device(device), len(insts), total, need)
+    bw = C.c_int32(0)
+    us = C.c_double(0)
+    _check(lib().pt_autotune(C.byref(desc), C.byref(sc.bufs), _stream_ptr(stream), int(trial_sweeps),
+                             C.byref(bw), C.byref(us)))
+    return int(bw.value), float(us.value)
 
 
 def instance_mutate(inst, alphabet, chain, seed, step, proposal):

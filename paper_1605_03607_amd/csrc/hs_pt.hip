@@ -1213,10 +1213,13 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
     return HS_OK;
 }
 
-int pt_sweep(hs_pt *h, int64_t n_sweeps)
+}  // extern "C"
+
+namespace {
+
+// Enqueues the work-queue reset and the persistent sweep kernel on `stream`.
+int sweep_launch(hs_pt *h, int64_t n_sweeps, hipStream_t stream)
 {
-    if (h == nullptr || n_sweeps < 0) return fail(HS_EINVAL, "pt_sweep: bad arguments");
-    if (h->n_inst == 0 || n_sweeps == 0) return HS_OK;
     char *ws = reinterpret_cast<char *>(h->buf.workspace);
     dev::SweepArgs a;
     a.inst = reinterpret_cast<const InstDev *>(ws + h->off_inst * 4);
@@ -1240,10 +1243,134 @@ int pt_sweep(hs_pt *h, int64_t n_sweeps)
     a.tshi_max = h->tshi_max;
     a.r_max = h->r_max;
     a.lds_ts_ok = h->lds_ts_ok;
-    hipLaunchKernelGGL(dev::k_reset_queue, dim3(1), dim3(1), 0, h->stream, a.queue);
-    hipLaunchKernelGGL(dev::k_pt_sweep, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, h->stream, a);
+    hipLaunchKernelGGL(dev::k_reset_queue, dim3(1), dim3(1), 0, stream, a.queue);
+    hipLaunchKernelGGL(dev::k_pt_sweep, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "pt_sweep: launch");
+    return HS_OK;
+}
+
+}  // namespace
+
+struct hs_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t stream = nullptr;
+};
+
+extern "C" {
+
+int pt_sweep(hs_pt *h, int64_t n_sweeps)
+{
+    if (h == nullptr || n_sweeps < 0) return fail(HS_EINVAL, "pt_sweep: bad arguments");
+    if (h->n_inst == 0 || n_sweeps == 0) return HS_OK;
+    return sweep_launch(h, n_sweeps, h->stream);
+}
+
+int pt_graph_create(hs_pt *h, int64_t n_sweeps, hs_graph **out)
+{
+    if (h == nullptr || out == nullptr || n_sweeps < 0) return fail(HS_EINVAL, "pt_graph_create: bad arguments");
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    if (h->n_inst == 0 || n_sweeps == 0) {
+        HIP_TRY(hipGraphCreate(&g, 0));
+    } else {
+        // capture on a private stream (the handle's stream may be the legacy default stream)
+        hipStream_t cs = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(cs);
+            return hip_fail(e, "pt_graph_create: begin capture");
+        }
+        const int rc = sweep_launch(h, n_sweeps, cs);
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (rc != HS_OK || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc != HS_OK ? rc : hip_fail(e2, "pt_graph_create: end capture");
+        }
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "pt_graph_create: instantiate");
+    }
+    auto G = new hs_graph();
+    G->graph = g;
+    G->exec = ex;
+    G->stream = h->stream;
+    *out = G;
+    return HS_OK;
+}
+
+int pt_graph_launch(hs_graph *g)
+{
+    if (g == nullptr) return fail(HS_EINVAL, "pt_graph_launch: NULL graph");
+    HIP_TRY(hipGraphLaunch(g->exec, g->stream));
+    return HS_OK;
+}
+
+int pt_graph_destroy(hs_graph *g)
+{
+    if (g == nullptr) return HS_OK;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return HS_OK;
+}
+
+int pt_autotune(const hs_pt_desc *d, const hs_buffers *scratch, void *stream, int64_t trial_sweeps,
+                int32_t *block_waves_out, double *us_per_sweep_out)
+{
+    if (d == nullptr || scratch == nullptr || block_waves_out == nullptr || trial_sweeps < 1)
+        return fail(HS_EINVAL, "pt_autotune: bad arguments");
+    const int cand[] = {2, 4, 8, 16};
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int best = 0;
+    double best_us = 0.0;
+    int rc = HS_OK;
+    for (int c : cand) {
+        hs_pt_desc dc = *d;
+        dc.block_waves = c;
+        dc.flags &= ~HS_INIT_FROM_BUFFER;
+        size_t need = 0;
+        rc = pt_workspace_bytes(&dc, &need);
+        if (rc != HS_OK) break;
+        if (need > scratch->workspace_bytes) continue;
+        hs_pt *h = nullptr;
+        rc = pt_init(&h, &dc, scratch, stream);
+        if (rc != HS_OK) break;
+        rc = pt_sweep(h, std::max<int64_t>(1, trial_sweeps / 8));  // warm-up
+        hipError_t e = hipSuccess;
+        if (rc == HS_OK) e = hipEventRecord(e0, st);
+        if (rc == HS_OK && e == hipSuccess) rc = pt_sweep(h, trial_sweeps);
+        if (rc == HS_OK && e == hipSuccess) e = hipEventRecord(e1, st);
+        if (rc == HS_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (rc == HS_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        pt_destroy(h);
+        if (rc != HS_OK) break;
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "pt_autotune: timing");
+            break;
+        }
+        const double us = double(ms) * 1e3 / double(trial_sweeps);
+        if (best == 0 || us < best_us) {
+            best = c;
+            best_us = us;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != HS_OK) return rc;
+    if (best == 0) return fail(HS_ENOSPACE, "pt_autotune: scratch workspace too small for every candidate");
+    *block_waves_out = best;
+    if (us_per_sweep_out) *us_per_sweep_out = best_us;
     return HS_OK;
 }
 
