@@ -122,3 +122,18 @@ def make_batch(cfg, n_inst=None):
 def search_seeds(n_chains=64, L=8, seed=2016):
     """Random +-1 seed instances for the instance-hardness search (Algorithm 1)."""
     return [couplings(L, "pm1", seed, c) for c in range(n_chains)]
+
+
+def gnn_params(n_params, fan_ins, seed=1605):
+    """Initial surrogate weights: uniform in +-sqrt(6 / (fan_in + 64)) per
+    block (fan_ins: list of (size, fan_in), fan_in 0 = zeros), float32."""
+    g = rng(seed, 777_777)
+    out = np.zeros(n_params, np.float32)
+    o = 0
+    for size, fan_in in fan_ins:
+        if fan_in > 0:
+            a = np.sqrt(6.0 / (fan_in + 64))
+            out[o:o + size] = g.uniform(-a, a, size).astype(np.float32)
+        o += size
+    assert o == n_params
+    return out
