@@ -56,6 +56,15 @@ class hs_hardness_params(C.Structure):
                 ("seed", C.c_uint32), ("block_waves", C.c_int32)]
 
 
+class hs_gnn_batch(C.Structure):
+    _fields_ = [("n_graphs", C.c_int32), ("L", C.c_int32), ("live", C.c_void_p), ("J", C.c_void_p)]
+
+
+class hs_adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int64), ("m", C.c_void_p), ("v", C.c_void_p)]
+
+
 class hs_tts_detail(C.Structure):
     _fields_ = [("e_gs", C.c_int32), ("confirmed", C.c_int32), ("n_censored", C.c_int32),
                 ("sweeps_total", C.c_int64)]
@@ -95,6 +104,14 @@ def lib():
         L.hardness_eval.argtypes = [C.POINTER(hs_instance), C.c_int, C.POINTER(hs_hardness_params),
                                     C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(hs_tts_detail),
                                     C.c_void_p]
+        L.gnn_param_count.restype = C.c_int
+        L.gnn_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+        L.gnn_prepare.argtypes = [C.POINTER(hs_gnn_batch), C.c_void_p, C.c_size_t, C.c_void_p]
+        L.gnn_forward.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                  C.c_void_p]
+        L.gnn_train_step.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.POINTER(hs_adam), C.c_void_p]
         _lib = L
     return _lib
 
@@ -122,7 +139,8 @@ def exported_symbols():
     return ["hs_version", "hs_last_error", "pt_workspace_bytes", "pt_init", "pt_sweep", "pt_swap",
             "pt_measure", "pt_destroy", "pt_graph_create", "pt_graph_launch", "pt_graph_destroy",
             "pt_autotune", "instance_mutate", "hs_rao_accept", "hardness_workspace_bytes",
-            "hardness_eval"]
+            "hardness_eval", "gnn_param_count", "gnn_workspace_bytes", "gnn_prepare", "gnn_forward",
+            "gnn_train_step"]
 
 
 def _check(rc):
@@ -342,3 +360,92 @@ def hardness_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed, blo
                     n_censored=det[i].n_censored, sweeps_total=det[i].sweeps_total)
                for i in range(len(cands))]
     return ln, details
+
+
+# ---------------------------------------------------------------------------
+# Hardness surrogate (include/hs_gnn.h).
+GNN_WIDTH = 64
+
+
+def gnn_fan_ins():
+    """(size, fan_in) of every parameter block, in the library's order."""
+    D = GNN_WIDTH
+    blocks = [(D * 5, 5), (D, 0), (D * 4, 4), (D, 0)]
+    for _ in range(3):
+        blocks += [(D * 3 * D, 3 * D), (D, 0), (D * 2 * D, 2 * D), (D, 0)]
+    return blocks + [(D, D), (1, 0)]
+
+
+class Surrogate:
+    """Parameters, Adam state and workspace of the surrogate on one device.
+
+    graphs: list of (L, live or None, J) with one L per call."""
+
+    def __init__(self, params, device="cuda", stream=None):
+        torch = _torch()
+        self.torch = torch
+        n = lib().gnn_param_count()
+        params = np.ascontiguousarray(params, np.float32)
+        if params.size != n:
+            raise ValueError(f"expected {n} parameters")
+        dev = torch.device(device)
+        self.params = torch.from_numpy(params.copy()).to(dev)
+        self.m = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.grad = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.step = 0
+        self.stream = stream
+        self.ws = None
+        self.shape = None
+
+    def prepare(self, graphs):
+        torch = self.torch
+        G = len(graphs)
+        L = int(graphs[0][0])
+        if any(int(g[0]) != L for g in graphs):
+            raise ValueError("one L per batch")
+        nb = C.c_size_t(0)
+        _check(lib().gnn_workspace_bytes(G, L, C.byref(nb)))
+        if self.ws is None or self.ws.numel() < nb.value:
+            self.ws = torch.zeros(nb.value, dtype=torch.uint8, device=self.params.device)
+        N = 8 * L * L
+        J = np.ascontiguousarray(np.concatenate([np.asarray(g[2], np.int8) for g in graphs]))
+        lives = [g[1] for g in graphs]
+        live = None
+        if any(x is not None for x in lives):
+            live = np.ascontiguousarray(np.concatenate(
+                [np.ones(N, np.uint8) if x is None else np.asarray(x, np.uint8) for x in lives]))
+        b = hs_gnn_batch(G, L, None if live is None else live.ctypes.data, J.ctypes.data)
+        _check(lib().gnn_prepare(C.byref(b), C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                 _stream_ptr(self.stream)))
+        self.shape = (G, L)
+
+    def forward(self, graphs=None):
+        """y_hat (numpy float32) of the prepared (or given) batch."""
+        if graphs is not None:
+            self.prepare(graphs)
+        G, L = self.shape
+        y = self.torch.zeros(G, dtype=self.torch.float32, device=self.params.device)
+        _check(lib().gnn_forward(C.c_void_p(self.params.data_ptr()), G, L, C.c_void_p(self.ws.data_ptr()),
+                                 self.ws.numel(), C.c_void_p(y.data_ptr()), _stream_ptr(self.stream)))
+        return y.cpu().numpy()
+
+    def train_step(self, labels, graphs=None, lr=1e-3, update=True, betas=(0.9, 0.999), eps=1e-8):
+        """One step on the prepared (or given) batch: (loss, y_hat); the
+        gradient stays in self.grad.  update=False leaves the parameters."""
+        torch = self.torch
+        if graphs is not None:
+            self.prepare(graphs)
+        G, L = self.shape
+        lab = torch.from_numpy(np.ascontiguousarray(labels, np.float32)).to(self.params.device)
+        y = torch.zeros(G, dtype=torch.float32, device=self.params.device)
+        adam = None
+        if update:
+            self.step += 1
+            adam = hs_adam(lr, betas[0], betas[1], eps, self.step, self.m.data_ptr(), self.v.data_ptr())
+        _check(lib().gnn_train_step(C.c_void_p(self.params.data_ptr()), G, L, C.c_void_p(lab.data_ptr()),
+                                    C.c_void_p(self.ws.data_ptr()), self.ws.numel(), C.c_void_p(y.data_ptr()),
+                                    C.c_void_p(self.loss.data_ptr()), C.c_void_p(self.grad.data_ptr()),
+                                    None if adam is None else C.byref(adam), _stream_ptr(self.stream)))
+        return float(self.loss.item()), y.cpu().numpy()

@@ -13,6 +13,8 @@ import workloads
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "hardspin.h")
+GNN_HEADER = os.path.join(ROOT, "include", "hs_gnn.h")
+PROBE_HEADER = os.path.join(ROOT, "include", "hs_probe.h")
 
 
 def _hs():
@@ -22,8 +24,8 @@ def _hs():
     return hs
 
 
-def _declared_functions():
-    text = open(HEADER).read()
+def _declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:int|const char \*)\s*\**\s*([a-z_]+)\s*\(", text, flags=re.M)
     return sorted(set(names))
@@ -42,12 +44,39 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", hs.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
-    missing = [n for n in _declared_functions() if n not in exported]
+    declared = _declared_functions() + _declared_functions(GNN_HEADER)
+    missing = [n for n in declared if n not in exported]
     assert not missing, missing
     lib = hs.lib()
     assert lib.hs_version() >= 10000
-    for n in _declared_functions():
+    for n in declared:
         assert hasattr(lib, n)
+
+
+def test_probe_library_exports_its_entry_point():
+    hs = _hs()
+    path = os.path.join(os.path.dirname(hs.LIB_PATH), "libhsprobe.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    names = _declared_functions(PROBE_HEADER)
+    assert names and all(n in exported for n in names)
+
+
+def test_gnn_host_entry_points():
+    """Parameter count matches the oracle's layout; the workspace grows with
+    the batch; malformed arguments are rejected without a GPU."""
+    import ctypes as C
+    import oracle.gnn as G
+    hs = _hs()
+    lib = hs.lib()
+    assert lib.gnn_param_count() == G.n_params()
+    a, b = C.c_size_t(0), C.c_size_t(0)
+    assert lib.gnn_workspace_bytes(1, 8, C.byref(a)) == 0
+    assert lib.gnn_workspace_bytes(16, 8, C.byref(b)) == 0
+    assert b.value > 10 * a.value > 0
+    assert lib.gnn_workspace_bytes(0, 8, C.byref(a)) == -1
+    assert lib.gnn_workspace_bytes(1, 17, C.byref(a)) == -1
 
 
 def test_library_has_gfx950_code():
