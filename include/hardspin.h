@@ -202,12 +202,14 @@ int hs_rao_accept(double ln_cur, double ln_new, double t_s, uint32_t w);
 
 /* Hardness of candidate instances: n_restarts independent PT runs per
  * candidate (restart rho keyed by (word 0 of Philox((instance_id, seed),
- * (rho, 0, 0, 5)), seed)), each until replica agreement or s_max sweeps; all
- * runs of all candidates share one persistent launch.  E_gs = min over
- * restarts; TTS_rho = max(1, first-hit sweep of E_gs), +inf if restart rho
- * never held E_gs; ln_tts = ln(lower median of TTS_rho) (+inf if censored).
- * Sec. III.B (ground-state agreement cross-check) and Appendix B (stop after
- * repeated agreement).  Requires R >= 2.  Blocks until done. */
+ * (rho, 0, 0, 5)), seed)), each until replica agreement or s_max sweeps
+ * (t_rho sweeps); all runs of all candidates share one persistent launch.
+ * E_gs = min over restarts; n_hit = restarts whose minimum is E_gs (>= 1);
+ * ln_tts = ln(sum of t_rho / n_hit), the run time per find of the presumed
+ * ground state, as Appendix B defines the time-to-solution (run time until
+ * the lowest energy has been found n+1 times, divided by n+1); Sec. III.B
+ * cross-checks ground-state energies by agreement.  detail->n_censored =
+ * restarts that ended above E_gs.  Requires R >= 2.  Blocks until done. */
 typedef struct hs_hardness_params {
     int32_t n_restarts;
     int32_t K;

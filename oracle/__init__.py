@@ -180,7 +180,8 @@ def lane_energies(L, live, J, lanes, spins):
 
 
 def hardness_eval(L, live, J, instance_id, seed, n_restarts, K, R, beta, swap_interval, s_max):
-    """Returns dict(ln_tts, e_gs, confirmed, r_emin, r_tts, r_sweeps); r_tts = -1 if censored."""
+    """Returns dict(ln_tts, e_gs, confirmed, r_emin, r_tts, r_sweeps); ln_tts = ln(sum r_sweeps /
+    restarts reaching e_gs); r_tts = first-hit sweep, -1 if the restart never reached e_gs."""
     keep, lp = _live_ptr(live)
     ln = np.zeros(1, np.float64)
     egs = np.zeros(1, np.int32)

@@ -33,7 +33,8 @@
  *   layout below; a 32-bit uniform u = (hi16 << 16) | lo16 drawn from two
  *   Philox domains; accept iff dE <= 0 or u < floor(2^32 exp(-beta dE));
  *   one ascending exchange pass per replica set after every swap_interval-th
- *   sweep; lower median of restart TTS in sweeps.
+ *   sweep; time-to-solution = restart sweeps per restart that reached the
+ *   ground state (Appendix B's run time per find of the minimum).
  *
  * Parity status: every function here is pinned by the not-gpu tests
  * (brute force, closed forms, Boltzmann statistics, gauge invariance,
@@ -541,16 +542,13 @@ int or_lane_energies(int L, const uint8_t *live, const int8_t *J, int lanes,
 /* Restart rho of a candidate with id `instance_id` uses the Philox key     */
 /* (word 0 of Philox((instance_id, seed), (rho, 0, 0, D_RESTART)), seed),   */
 /* starts from the Philox initial state and runs until agreement or s_max   */
-/* sweeps.  E_gs = min over restarts; TTS_rho = max(1, first sweep at which */
-/* restart rho held E_gs in some replica set), +inf (censored) if it never */
-/* did.  ln_tts = ln(lower median of TTS_rho).  confirmed = 1 when E_gs was */
-/* reached by two restarts, or by two replica sets of one restart.          */
+/* sweeps (t_rho).  E_gs = min over restarts.  ln_tts = ln(sum t_rho /      */
+/* n_hit), n_hit = restarts whose minimum is E_gs (Appendix B's run time    */
+/* per repeated find of the presumed minimum).  r_tts: first sweep at which */
+/* restart rho held E_gs (max 1), -1 if it never did (censored).            */
+/* confirmed = 1 when E_gs was reached by two restarts, or by two replica   */
+/* sets of one restart.                                                     */
 /* ------------------------------------------------------------------------ */
-static int cmp_double(const void *a, const void *b)
-{
-    double x = *(const double *)a, y = *(const double *)b;
-    return (x > y) - (x < y);
-}
 
 int or_hardness_eval(int L, const uint8_t *live, const int8_t *J, uint32_t instance_id,
                      uint32_t seed, int n_restarts, int K, int R, const double *beta,
@@ -589,7 +587,6 @@ int or_hardness_eval(int L, const uint8_t *live, const int8_t *J, uint32_t insta
     for (int rho = 1; rho < n_restarts; ++rho)
         if (r_emin[rho] < gs) gs = r_emin[rho];
     int hits = 0, double_hit = 0;
-    double *tts = (double *)malloc(sizeof(double) * (size_t)n_restarts);
     for (int rho = 0; rho < n_restarts; ++rho) {
         int64_t best = -1;
         int sets = 0;
@@ -603,18 +600,20 @@ int or_hardness_eval(int L, const uint8_t *live, const int8_t *J, uint32_t insta
             ++hits;
             if (best < 1) best = 1;
             r_tts[rho] = best;
-            tts[rho] = (double)best;
         } else {
             r_tts[rho] = -1;
-            tts[rho] = INFINITY;
         }
     }
-    qsort(tts, (size_t)n_restarts, sizeof(double), cmp_double);
-    double med = tts[(n_restarts - 1) / 2];
-    *ln_tts = isinf(med) ? INFINITY : log(med);
+    /* Appendix B: the time-to-solution is the run time spent until the
+     * presumed minimum has been found n+1 times, divided by n+1.  Each
+     * restart is one independent search that ends at its own presumed
+     * minimum (replica agreement); so TTS = sweeps of all restarts / number
+     * of restarts whose minimum is E_gs (at least one). */
+    int64_t total = 0;
+    for (int rho = 0; rho < n_restarts; ++rho) total += r_sweeps[rho];
+    *ln_tts = log((double)(total > 0 ? total : 1) / (double)hits);
     *e_gs = gs;
     *confirmed = (hits >= 2 || double_hit) ? 1 : 0;
-    free(tts);
     free(rset_emin);
     free(rset_thit);
     free(spins);

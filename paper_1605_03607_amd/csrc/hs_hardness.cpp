@@ -152,30 +152,20 @@ int hardness_eval(const hs_instance *cands, int n, const hs_hardness_params *p, 
             for (int r = 0; r < R; ++r) gs = std::min(gs, emin[(size_t(c) * nr + rho) * 64 + r]);
         int hits = 0, double_hit = 0, censored = 0;
         int64_t sweeps = 0;
-        std::vector<double> tts(nr);
         for (int rho = 0; rho < nr; ++rho) {
             const size_t run = size_t(c) * nr + rho;
             sweeps += t[run];
-            int64_t best = -1;
             int sets = 0;
-            for (int r = 0; r < R; ++r)
-                if (emin[run * 64 + r] == gs) {
-                    ++sets;
-                    const int64_t th = thit[run * 64 + r];
-                    if (best < 0 || th < best) best = th;
-                }
+            for (int r = 0; r < R; ++r) sets += emin[run * 64 + r] == gs ? 1 : 0;
             if (sets >= 2) double_hit = 1;
-            if (best >= 0) {
+            if (sets > 0)
                 ++hits;
-                tts[rho] = double(std::max<int64_t>(best, 1));
-            } else {
+            else
                 ++censored;
-                tts[rho] = INFINITY;
-            }
         }
-        std::sort(tts.begin(), tts.end());
-        const double med = tts[(nr - 1) / 2];
-        ln_tts_out[c] = std::isinf(med) ? INFINITY : std::log(med);
+        // run time per find of the presumed minimum (Appendix B): all restart
+        // sweeps over the restarts that ended at E_gs (at least one does)
+        ln_tts_out[c] = std::log(double(std::max<int64_t>(sweeps, 1)) / double(hits));
         if (detail) {
             detail[c].e_gs = gs;
             detail[c].confirmed = (hits >= 2 || double_hit) ? 1 : 0;
