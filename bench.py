@@ -72,9 +72,12 @@ def parse():
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed steps, run one plain device copy of this many MiB "
                         "(reference kernel for scaling HBM byte counters)")
-    p.add_argument("--workload", choices=["c8", "uneven"], default="c8",
+    p.add_argument("--workload", choices=["c8", "uneven", "search"], default="c8",
                    help="c8: the 256 x C8 batch (default); uneven: 1024 instances C4..C12, "
-                        "autotuned shape, HIP-graph replay, live attempts/s")
+                        "autotuned shape, HIP-graph replay, live attempts/s; search: bounded "
+                        "plain / surrogate-screened / random-screened instance search")
+    p.add_argument("--search-steps", type=int, default=20)
+    p.add_argument("--search-chains", type=int, default=64)
     p.add_argument("--probe", action="store_true",
                    help="also measure instruction issue rates (libhsprobe.so)")
     return p.parse_args()
@@ -182,6 +185,58 @@ def uneven(args):
     print(json.dumps(out), flush=True)
 
 
+def search(args):
+    """Hard instances per hour of the instance search (Algorithm 1) on C8:
+    plain chains, surrogate-screened chains and the random-screen ablation,
+    each for a bounded number of steps from the same seed instances."""
+    import math
+
+    import paper_1605_03607_amd as hs
+    from paper_1605_03607_amd import search as S
+    seeds = workloads.search_seeds(args.search_chains)
+    bars = {"ln3": math.log(3.0), "ln10": math.log(10.0), "ln30": math.log(30.0)}
+    arms = {}
+    for mode in ("plain", "surrogate", "random"):
+        cfg = S.SearchConfig(mode=mode, chains=args.search_chains)
+        params = workloads.gnn_params(hs.lib().gnn_param_count(), hs.gnn_fan_ins())
+        t0 = time.perf_counter()
+        run = S.Search(cfg, seeds, surrogate_params=params if mode == "surrogate" else None)
+        t_init = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for k in range(args.search_steps):
+            run.run_step(bars=tuple(bars.values()))
+            print(f"# {mode}: step {k + 1}/{args.search_steps}", file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        hours = wall / 3600.0
+        hard = {name: len(run.hard.get(b, set())) for name, b in bars.items()}
+        finite = np.isfinite(run.ln)
+        arms[mode] = {
+            "steps": args.search_steps, "seconds": wall, "s_per_step": wall / args.search_steps,
+            "init_seconds": t_init, "pt_seconds": run.pt_seconds, "gnn_seconds": run.gnn_seconds,
+            "pt_sweeps": int(run.pt_sweeps), "accepted": run.accepted, "h0_ln_tts": run.h0,
+            "hard_instances": hard,
+            "hard_instances_per_hour": {k: v / hours for k, v in hard.items()},
+            "final_median_ln_tts_finite": float(np.median(run.ln[finite])) if finite.any() else None,
+            "final_censored_chains": int((~finite).sum()),
+        }
+    rate = lambda m: arms[m]["hard_instances_per_hour"]["ln10"]
+    out = {
+        "metric": "hard instances/hour, surrogate vs plain",
+        "value": rate("surrogate"),
+        "unit": "hard instances/hour (ln TTS >= H0 + ln 10)",
+        "n_gpus": 1, "steps": args.search_steps, "warmup": 0,
+        "ms_per_step": arms["surrogate"]["s_per_step"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32 (PT) / bf16-fp32 (surrogate)", "data": "synthetic",
+        "config": {"workload": f"instance search, {args.search_chains} C8 chains, +-1 seeds, "
+                               "mutations in +-1..+-7, 32 restarts K32 R2, T_s 0.5",
+                   "bounded_steps": args.search_steps},
+        "surrogate_over_plain": (rate("surrogate") / rate("plain")) if rate("plain") > 0 else None,
+        "arms": arms,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -189,6 +244,9 @@ def main():
         sys.exit(2)
     if args.workload == "uneven":
         uneven(args)
+        return
+    if args.workload == "search":
+        search(args)
         return
     import torch
 

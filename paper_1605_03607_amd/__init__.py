@@ -80,6 +80,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1605_03607_amd.build`")
+        # torch ships its own HIP runtime under the same soname: load it first so
+        # that the library and torch share one runtime
+        _torch()
         L = C.CDLL(LIB_PATH)
         L.hs_version.restype = C.c_int
         L.hs_last_error.restype = C.c_char_p
@@ -123,6 +126,7 @@ PROBE_NAMES = ["v_add_u32", "v_bitop3_b32", "v_mad_u64_u32", "v_mul_hi_u32", "v_
 def probe_rates(iters=2000):
     """Measured lane-ops/s of each instruction class (libhsprobe.so)."""
     torch = _torch()
+    lib()
     path = os.path.join(HERE, "libhsprobe.so")
     P = C.CDLL(path)
     P.hs_probe_rate.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), C.c_void_p]

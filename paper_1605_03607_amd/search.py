@@ -1,0 +1,153 @@
+"""Instance-space search driven by the gfx950 engine (Algorithm 1, Sec. II.A).
+
+Every chain holds one instance J.  A step proposes coupler mutations
+(instance_mutate), scores candidates with hardness_eval (ln of the median
+time-to-solution over independent PT restarts, in sweeps) and accepts by
+Metropolis in ln TTS at search temperature t_s (hs_rao_accept).  Three modes:
+
+  plain      one proposal per chain, scored by PT (Algorithm 1 as written)
+  surrogate  `proposals` mutations per chain ranked by the surrogate network;
+             the `top` best go to PT, the one with the larger PT score (ties:
+             lower proposal index) enters the acceptance test; the network
+             is trained online on every PT-scored (J, ln TTS) pair
+  random     as surrogate, but the `top` candidates are chosen at random
+             (the ablation: what ranking by the network gains)
+
+PT stays the judge of every accepted instance.  A hard instance is an
+accepted state with ln TTS >= H0 + ln(bar), H0 = median ln TTS of the seed
+instances; distinct hard instances are counted by their couplings.
+"""
+import hashlib
+import math
+import time
+
+import numpy as np
+
+from . import Surrogate, gnn_fan_ins, hardness_eval, instance_mutate, rao_accept
+
+ALPHABET_PM7 = np.array([-7, -6, -5, -4, -3, -2, -1, 1, 2, 3, 4, 5, 6, 7], np.int8)
+
+
+def _geometric(lo, hi, k):
+    return lo * (hi / lo) ** (np.arange(k) / (k - 1))
+
+
+class SearchConfig:
+    def __init__(self, mode="plain", chains=64, L=8, restarts=32, K=32, R=2, beta=(0.1, 5.0),
+                 swap_interval=1, s_max=100_000, t_s=0.5, seed=1605, proposals=16, top=2,
+                 train_steps=4, train_batch=16, lr=1e-3, replay=4096, screen_chunk=128):
+        self.mode = mode
+        self.chains, self.L, self.restarts, self.K, self.R = chains, L, restarts, K, R
+        self.beta = _geometric(beta[0], beta[1], K)
+        self.swap_interval, self.s_max, self.t_s, self.seed = swap_interval, s_max, t_s, seed
+        self.proposals = 1 if mode == "plain" else proposals
+        self.top = 1 if mode == "plain" else top
+        self.train_steps, self.train_batch, self.lr = train_steps, train_batch, lr
+        self.replay, self.screen_chunk = replay, screen_chunk
+
+
+def _key(J):
+    return hashlib.sha1(np.ascontiguousarray(J, np.int8).tobytes()).hexdigest()
+
+
+class Search:
+    def __init__(self, cfg, seeds, surrogate_params=None):
+        self.cfg = cfg
+        self.J = [np.array(s, np.int8) for s in seeds]
+        self.step = 0
+        self.pt_seconds = 0.0
+        self.gnn_seconds = 0.0
+        self.pt_sweeps = 0
+        self.pairs_J, self.pairs_y = [], []
+        self.sur = None
+        if cfg.mode == "surrogate":
+            self.sur = Surrogate(surrogate_params)
+        self.rng = np.random.default_rng(cfg.seed + 77)
+        self.ln = self._score([dict(L=cfg.L, J=J, live=None, instance_id=c) for c, J in enumerate(self.J)])
+        self.h0 = float(np.median(self.ln))
+        self.accepted = 0
+        self.hard = {}
+
+    def _score(self, cands):
+        c = self.cfg
+        t0 = time.perf_counter()
+        ln, det = hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
+        self.pt_seconds += time.perf_counter() - t0
+        self.pt_sweeps += sum(d["sweeps_total"] for d in det)
+        for cd, y in zip(cands, ln):
+            if math.isfinite(y):
+                self.pairs_J.append(np.array(cd["J"], np.int8))
+                self.pairs_y.append(float(y))
+        if len(self.pairs_J) > c.replay:
+            self.pairs_J = self.pairs_J[-c.replay:]
+            self.pairs_y = self.pairs_y[-c.replay:]
+        return ln
+
+    def _proposals(self, chain):
+        c = self.cfg
+        out = []
+        for p in range(c.proposals):
+            e, old, new, w = instance_mutate(dict(L=c.L, J=self.J[chain], live=None), ALPHABET_PM7, chain,
+                                             c.seed, self.step, p)
+            J2 = self.J[chain].copy()
+            J2[e] = new
+            out.append((J2, w, p))
+        return out
+
+    def _rank(self, props):
+        """Surrogate predictions for every (chain, proposal)."""
+        c = self.cfg
+        flat = [J for pr in props for (J, _, _) in pr]
+        t0 = time.perf_counter()
+        pred = []
+        for a in range(0, len(flat), c.screen_chunk):
+            pred.append(self.sur.forward([(c.L, None, J) for J in flat[a:a + c.screen_chunk]]))
+        self.gnn_seconds += time.perf_counter() - t0
+        return np.concatenate(pred).reshape(len(props), c.proposals)
+
+    def _train(self):
+        c = self.cfg
+        if self.sur is None or len(self.pairs_J) < c.train_batch:
+            return
+        t0 = time.perf_counter()
+        for _ in range(c.train_steps):
+            idx = self.rng.choice(len(self.pairs_J), size=c.train_batch, replace=False)
+            self.sur.train_step(np.array([self.pairs_y[i] for i in idx]),
+                                graphs=[(c.L, None, self.pairs_J[i]) for i in idx], lr=c.lr)
+        self.gnn_seconds += time.perf_counter() - t0
+
+    def run_step(self, bars=(math.log(3.0), math.log(10.0), math.log(30.0))):
+        c = self.cfg
+        props = [self._proposals(ch) for ch in range(c.chains)]
+        if c.mode == "plain":
+            chosen = [[0] for _ in range(c.chains)]
+        elif c.mode == "surrogate":
+            pred = self._rank(props)
+            chosen = [sorted(np.argsort(-pred[ch], kind="stable")[:c.top].tolist()) for ch in range(c.chains)]
+        else:
+            chosen = [sorted(self.rng.choice(c.proposals, size=c.top, replace=False).tolist())
+                      for _ in range(c.chains)]
+        cands, owner = [], []
+        for ch in range(c.chains):
+            for p in chosen[ch]:
+                J2, _, _ = props[ch][p]
+                cands.append(dict(L=c.L, J=J2, live=None, instance_id=ch))
+                owner.append((ch, p))
+        ln = self._score(cands)
+        best = {}
+        for (ch, p), y in zip(owner, ln):
+            if ch not in best or y > best[ch][1]:  # ties keep the lower proposal index
+                best[ch] = (p, y)
+        for ch in range(c.chains):
+            p, y = best[ch]
+            J2, w, _ = props[ch][p]
+            if rao_accept(self.ln[ch], y, c.t_s, w):
+                self.J[ch] = J2
+                self.ln[ch] = y
+                self.accepted += 1
+                for b in bars:
+                    if y >= self.h0 + b:
+                        self.hard.setdefault(b, set()).add(_key(J2))
+        self._train()
+        self.step += 1
+
