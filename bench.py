@@ -72,7 +72,7 @@ def parse():
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed steps, run one plain device copy of this many MiB "
                         "(reference kernel for scaling HBM byte counters)")
-    p.add_argument("--workload", choices=["c8", "uneven", "search"], default="c8",
+    p.add_argument("--workload", choices=["c8", "uneven", "search", "surrogate"], default="c8",
                    help="c8: the 256 x C8 batch (default); uneven: 1024 instances C4..C12, "
                         "autotuned shape, HIP-graph replay, live attempts/s; search: bounded "
                         "plain / surrogate-screened / random-screened instance search")
@@ -237,6 +237,49 @@ def search(args):
     print(json.dumps(out), flush=True)
 
 
+def surrogate(args):
+    """Surrogate step times on C8 graphs: a training step (forward, backward,
+    Adam) on the 16-graph batch and the forward pass that screens 1024
+    proposals (64 chains x 16), with the MFMA-priced FLOP rate."""
+    import torch
+
+    import paper_1605_03607_amd as hs
+    n_par = hs.lib().gnn_param_count()
+    sur = hs.Surrogate(workloads.gnn_params(n_par, hs.gnn_fan_ins()))
+    L = 8
+    E = 24 * L * L - 8 * L
+    N = 8 * L * L
+
+    def flops(G):  # matrix products of one forward pass
+        ne, nn = 2 * E * G, N * G
+        return 3 * 2 * 64 * (ne * 192 + nn * 128)
+
+    out = {}
+    for G, what in ((16, "train"), (1024, "forward")):
+        gr = [(L, None, workloads.couplings(L, "pm7", 99, g)) for g in range(G)]
+        sur.prepare(gr)
+        labels = np.linspace(5.0, 12.0, G)
+        reps = 20 if what == "train" else 5
+        for _ in range(2):
+            sur.train_step(labels, update=False) if what == "train" else sur.forward()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            if what == "train":
+                sur.train_step(labels)
+            else:
+                sur.forward()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        f = flops(G) * (3 if what == "train" else 1)
+        out[what] = {"graphs": G, "ms": dt * 1e3, "tflops": f / dt / 1e12}
+    res = {"metric": "surrogate step time (C8 graphs)", "value": out["train"]["ms"], "unit": "ms per training step",
+           "n_gpus": 1, "steps": 20, "warmup": 2, "higher_is_better": False, "dtype": "bf16 (fp32 accumulate)",
+           "data": "synthetic", "config": {"workload": "surrogate, 16-graph training batch, 1024-graph screen"},
+           "detail": out, "mfma_peak_tflops_bf16": 2500.0}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -247,6 +290,9 @@ def main():
         return
     if args.workload == "search":
         search(args)
+        return
+    if args.workload == "surrogate":
+        surrogate(args)
         return
     import torch
 
