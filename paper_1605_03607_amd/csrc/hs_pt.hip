@@ -203,7 +203,7 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int
     l.S = o;
     o += (uint32_t(ncell_max) * 2 + 1) * 64 * 4;  // spin rows, then one zero row
     l.ths = o;
-    o += uint32_t(kMRow) * 64 * 4;                // threshold columns by slot index
+    o += uint32_t(kMRow) * 64 * 2;                // 16-bit threshold columns by slot index
     l.tshi = o;
     o += ((uint32_t(tshi_max) * 2 + 15) / 16) * 16;
     l.Eacc = o;
@@ -420,9 +420,11 @@ __host__ __device__ inline QuadRows quad_rows(int cell, int p, int Lc, int ncell
 // Dot products and the spin multiply use the compiler builtins, not inline
 // assembly: the wait states a dot-instruction result needs before a dependent
 // read are inserted only for instructions the compiler itself generates.
+// The clamp flag selects the three-operand encoding, whose zero accumulator
+// is an inline constant; the sums here are far from saturating.
 __device__ __forceinline__ int dot4_0(uint32_t a, uint32_t b)
 {
-    return __builtin_amdgcn_sdot4(int(a), int(b), 0, false);
+    return __builtin_amdgcn_sdot4(int(a), int(b), 0, true);
 }
 
 __device__ __forceinline__ int dot4_acc(uint32_t a, uint32_t b, int c)
@@ -435,6 +437,34 @@ template <int K>
 __device__ __forceinline__ int mul_spin(uint32_t own, int h4)
 {
     return __mul24(int(int8_t(uint8_t(own >> (8 * K)))), h4);
+}
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Per 16-bit half: saturating t' - u' of sign-flipped thresholds and
+// uniforms (t' = t ^ 0x8000, so the signed difference has the sign of t - u
+// and is zero iff t == u).
+__device__ __forceinline__ uint32_t sub_sat16x2(uint32_t a, uint32_t b)
+{
+    s16x2 x, y;
+    __builtin_memcpy(&x, &a, 4);
+    __builtin_memcpy(&y, &b, 4);
+    const s16x2 d = __builtin_elementwise_sub_sat(x, y);
+    uint32_t r;
+    __builtin_memcpy(&r, &d, 4);
+    return r;
+}
+
+__device__ __forceinline__ uint32_t min_u16x2(uint32_t a, uint32_t b)
+{
+    u16x2 x, y;
+    __builtin_memcpy(&x, &a, 4);
+    __builtin_memcpy(&y, &b, 4);
+    const u16x2 d = __builtin_elementwise_min(x, y);
+    uint32_t r;
+    __builtin_memcpy(&r, &d, 4);
+    return r;
 }
 
 // 4 m = 2 dE of site k of a cell side: h4 = -4 h from the opposite side
@@ -465,7 +495,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nwaves = __builtin_amdgcn_readfirstlane(int(blockDim.x >> 6));
     uint32_t *S = reinterpret_cast<uint32_t *>(lds + L.S);
-    uint32_t *THS = reinterpret_cast<uint32_t *>(lds + L.ths);
+    uint16_t *THS = reinterpret_cast<uint16_t *>(lds + L.ths);
     int32_t *Eacc = reinterpret_cast<int32_t *>(lds + L.Eacc);
     int32_t *perm = reinterpret_cast<int32_t *>(lds + L.perm);
     int32_t *slot = reinterpret_cast<int32_t *>(lds + L.slot);
@@ -513,7 +543,10 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         for (int i = tid; i < kMRow * 64; i += blockDim.x) {
             const int m = i >> 6, sx = i & 63;
             const int k = sx < nlanes ? sx % K : 0;
-            THS[i] = a.ws32[tb.thi_off + k * kMRow + m];
+            const uint32_t th = a.ws32[tb.thi_off + k * kMRow + m];
+            // 0x10000 ("always", m <= 0) becomes 0xFFFF: a uniform of 0xFFFF then
+            // ties and the exact pass accepts
+            THS[i] = uint16_t((th >= 0x10000u ? 0xFFFFu : th) ^ 0x8000u);
         }
         if (a.lds_ts_ok) {
             const uint32_t *src = a.ws32 + tb.ts_hi_off;
@@ -570,8 +603,8 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             const int kslot = min(sl & 0xFF, K - 1);
             const uint32_t sidx = live ? uint32_t((sl >> 8) * K + kslot) : uint32_t(lane);
             const uint32_t sword = (uint32_t(sl & 0xFF) << 8) | uint32_t(sl >> 8);
-            // threshold column of this lane's slot, entry m at byte m * 256
-            const uint32_t thl_base = L.ths + uint32_t(kMaxM) * 256u + sidx * 4u;
+            // threshold column of this lane's slot, entry m at byte m * 128
+            const uint32_t thl_base = L.ths + uint32_t(kMaxM) * 128u + sidx * 2u;
             MetroLane ml;
             {
                 uint32_t h, l;
@@ -628,29 +661,29 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         const int m1 = site_m4<1>(o0[h], oth[h], x01, jq[1], jq[5]);
                         const int m2 = site_m4<2>(o0[h], oth[h], x23, jq[2], jq[6]);
                         const int m3 = site_m4<3>(o0[h], oth[h], x23, jq[3], jq[7]);
-                        const uint32_t t0 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m0 * 64);
-                        const uint32_t t1 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m1 * 64);
-                        const uint32_t t2 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m2 * 64);
-                        const uint32_t t3 = *reinterpret_cast<const uint32_t *>(lds + thl_base + m3 * 64);
-                        const uint32_t wlo = h == 0 ? rw.x : rw.z;
-                        const uint32_t whi = h == 0 ? rw.y : rw.w;
-                        // d = thi - u16: accept iff d >= 0, tie iff d == 0
-                        const int d0 = int(t0) - int(wlo & 0xFFFFu), d1 = int(t1) - int(wlo >> 16);
-                        const int d2 = int(t2) - int(whi & 0xFFFFu), d3 = int(t3) - int(whi >> 16);
-                        tmin = min(tmin, min(min(uint32_t(d0), uint32_t(d1)), min(uint32_t(d2), uint32_t(d3))));
-                        const int s0 = d0 >> 31, s1 = d1 >> 31, s2 = d2 >> 31, s3 = d3 >> 31;  // -1 = reject
-                        // reject bytes R (0xFF where rejected); flip = ~R & fm (fm = 0xFE per live site)
-                        const uint32_t r01 = __builtin_amdgcn_perm(uint32_t(s1), uint32_t(s0), 0x0c0c0400u);
-                        const uint32_t r23 = __builtin_amdgcn_perm(uint32_t(s3), uint32_t(s2), 0x04000c0cu);
-                        const uint32_t rej = r01 | r23;
+                        // sign-flipped 16-bit thresholds of the four sites (m4 * 32 = m * 128 bytes)
+                        const uint32_t t0 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m0 * 32);
+                        const uint32_t t1 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m1 * 32);
+                        const uint32_t t2 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m2 * 32);
+                        const uint32_t t3 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m3 * 32);
+                        const uint32_t u01 = (h == 0 ? rw.x : rw.z) ^ 0x80008000u;
+                        const uint32_t u23 = (h == 0 ? rw.y : rw.w) ^ 0x80008000u;
+                        // per site d = t - u (16-bit, saturated): accept iff d > 0, tie iff d == 0
+                        const uint32_t d01 = sub_sat16x2(t0 | (t1 << 16), u01);
+                        const uint32_t d23 = sub_sat16x2(t2 | (t3 << 16), u23);
+                        tmin = min_u16x2(tmin, min_u16x2(d01, d23));
+                        // reject bytes (0xFF where d < 0): the sign bits of bytes 1, 3, 5, 7
+                        const uint32_t rej = __builtin_amdgcn_perm(d23, d01, 0x0B0A0908u);
                         if (p == 1 && (h == 0 || second)) {
-                            // (m4 ^ s) - s = m4 if accepted, -m4 if rejected
-                            e4 += (m0 ^ s0) + (m1 ^ s1) + (m2 ^ s2) + (m3 ^ s3);
+                            // (m4 ^ s) - s = m4 if accepted, -m4 if rejected (s = -1 on reject)
+                            e4 += (m0 ^ int(int8_t(rej))) + (m1 ^ int(int8_t(rej >> 8))) +
+                                  (m2 ^ int(int8_t(rej >> 16))) + (m3 ^ int(int8_t(rej >> 24)));
                             nrej += __builtin_popcount(rej);
                         }
+                        // flip = ~R & fm (fm = 0xFE per live site)
                         nw[h] = o0[h] ^ (~rej & fm);
                     }
-                    if (__any(tmin == 0u)) {
+                    if (__any((tmin & 0xFFFFu) == 0u || (tmin >> 16) == 0u)) {
                         // exact pass for this pair: full 32-bit uniforms
                         const MetroUniform mlo = metro_uniform(tt, kUseMetroLo, key0, key1);
                         const uint4 rl = metro_call(ml, mlo, c1, RK);
