@@ -95,6 +95,9 @@ __device__ __forceinline__ uint32_t in_vgpr(uint32_t s)
 }
 
 // The ten round keys of Philox4x32-10 for key (k0, k1): (k0 + r W0, k1 + r W1).
+// Bias that maps unsigned 16-bit halves onto signed ones with the same order.
+constexpr uint32_t kBias16 = 0x80008000u;
+
 struct RoundKeys {
     uint32_t a[10], b[10];
 };
@@ -207,7 +210,7 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int
     l.tshi = o;
     o += ((uint32_t(tshi_max) * 2 + 15) / 16) * 16;
     l.Eacc = o;
-    o += 2 * 64 * 4;                              // lane energies, double-buffered by sweep parity
+    o += 2 * 64 * 4;                              // slot energies (set-major), double-buffered by sweep parity
     l.perm = o;
     o += 64 * 4;
     l.slot = o;
@@ -271,6 +274,9 @@ __device__ __forceinline__ uint32_t exchange_uniform(uint32_t t, uint32_t use, i
 // that started at the beginning j of the current run of accepted exchanges
 // (a rejection at k starts a new run at k + 1).
 //
+// Slots are numbered set-major, s = r K + k (set r, temperature k); Es[s] is
+// the energy of the configuration at slot s.
+//
 // Step 1 (every wavefront): for each set r and start j, stop(j) = the first
 // pair k >= j rejected when slot k holds the configuration from slot j
 // (K - 1 if none).  The R (K-1) K / 2 tests (r, j <= k) are spread one per
@@ -290,17 +296,13 @@ __device__ __forceinline__ void load_xrows(int32_t *xrow, const TableDev &tb, co
 }
 
 template <bool kLds>
-__device__ void exchange_stops(int K, int R, int tri, uint32_t tri_m, int wave, int nwaves, const int32_t *E,
-                               const int32_t *perm, const uint32_t *ux, const int32_t *xrow, int32_t *stopv,
-                               const TableDev &tb, const uint32_t *ws32, const uint16_t *tshi)
+__device__ void exchange_stops(int K, int R, int tri, uint32_t tri_m, int wave, int nwaves, const int32_t *Es,
+                               const uint32_t *ux, const int32_t *xrow, int32_t *stopv, const TableDev &tb,
+                               const uint32_t *ws32, const uint16_t *tshi)
 {
     const int lane = threadIdx.x & 63;
     const int ntest = tri * R;
     if (wave * 64 >= ntest) return;
-    // per-lane values, gathered by the tests with bpermute
-    const int es = E[perm[lane] & 63];  // energy of the configuration at slot index k R + r
-    const uint32_t uxv = ux[lane];      // uniform of pair r (K-1) + k
-    const int rowv = xrow[lane], dhiv = xrow[64 + lane];
     const uint16_t *ghi = reinterpret_cast<const uint16_t *>(ws32 + tb.ts_hi_off);
     for (int base = wave * 64; base < ntest; base += nwaves * 64) {
         const int q = min(base + lane, ntest - 1);
@@ -310,10 +312,10 @@ __device__ void exchange_stops(int K, int R, int tri, uint32_t tri_m, int wave, 
         k += ((k + 1) * (k + 2) / 2 <= rem) ? 1 : 0;
         k -= (k * (k + 1) / 2 > rem) ? 1 : 0;
         const int j = rem - k * (k + 1) / 2;
-        const int ex = __shfl(es, j * R + r, 64);
-        const int ey = __shfl(es, (k + 1) * R + r, 64);
-        const uint32_t u = __shfl(uxv, r * (K - 1) + k, 64);
-        const int row = __shfl(rowv, k, 64), dh = __shfl(dhiv, k, 64);
+        const int ex = Es[r * K + j];
+        const int ey = Es[r * K + k + 1];
+        const uint32_t u = ux[r * (K - 1) + k];
+        const int row = xrow[k], dh = xrow[64 + k];
         const int d = ex - ey;
         const int at = row + min(max(d, 1), max(dh, 1)) - 1;  // clamped into the row
         uint32_t h;
@@ -336,45 +338,43 @@ __device__ void exchange_stops(int K, int R, int tri, uint32_t tri_m, int wave, 
     }
 }
 
-// Step 2 (one wavefront, lane l = r K + j): follow the run starts 0,
-// stop(0) + 1, ... of every set by binary lifting: jump tables
-// next^(2^m)(j) with next(j) = stop(j) + 1 (K = past the end), then every
-// slot k finds the last run start <= k.  Slot k of a run that starts at j
-// receives the configuration from slot k + 1 if k < stop(j) (accepted) and
-// the carried configuration from slot j if k = stop(j).
-__device__ void exchange_apply(int K, int R, uint32_t k_m, int32_t *perm, int32_t *slot, uint32_t *sacc,
+// Step 2 (wavefront r mod nwaves for set r, lane j): the run ends of set r
+// are stop(0), stop(stop(0) + 1), ... up to K - 1, found by a scalar walk
+// that reads stop(j) from lane j.  Slot k of the run [x, e] receives the
+// configuration from slot k + 1 if k < e (accepted) and the carried
+// configuration from slot x if k = e.  perm is slot -> lane (set-major),
+// slot is lane -> (k | r << 8) and sacc counts accepted exchanges by pair
+// k R + r.  Sets are disjoint, so the wavefronts of different sets touch
+// disjoint entries.
+__device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm, int32_t *slot, uint32_t *sacc,
                                int32_t *stopv)
 {
-    const int lane = threadIdx.x & 63;
-    const int r = int((uint32_t(lane) * k_m) >> 16);  // lane / K
-    const int j = lane - r * K;
-    const bool valid = lane < K * R;
-    const int base = r * K;
-    int J[6];
-    J[0] = K;
-    if (valid && j < K - 1) {
-        J[0] = stopv[r * 64 + j] + 1;
-        stopv[r * 64 + j] = K - 1;  // ready for the next pass
-    }
-#pragma unroll
-    for (int m = 1; m < 6; ++m) {
-        const int y = __shfl(J[m - 1], base + min(J[m - 1], K - 1), 64);
-        J[m] = J[m - 1] >= K ? K : y;
-    }
-    int x = 0;
-#pragma unroll
-    for (int m = 5; m >= 0; --m) {
-        const int y = __shfl(J[m], base + x, 64);
-        x = y <= j ? y : x;
-    }
-    const int st = __shfl(J[0], base + x, 64) - 1;  // stop of the run holding slot j
-    if (valid) {
-        const int oj = perm[x * R + r];
-        const int on = perm[min(j + 1, K - 1) * R + r];
-        const int np = j == st ? oj : on;
-        perm[j * R + r] = np;
-        slot[np] = j | (r << 8);
-        if (j < K - 1 && j != st) sacc[j * R + r] += 1u;
+    const int j = threadIdx.x & 63;
+    for (int r = wave; r < R; r += nwaves) {
+        const int base = r * K;
+        int st = K - 1;
+        if (j < K - 1) {
+            st = stopv[r * 64 + j];
+            stopv[r * 64 + j] = K - 1;  // ready for the next pass
+        }
+        uint64_t ends = 0;
+        int x0 = 0;
+        do {
+            const int e = __builtin_amdgcn_readlane(st, x0);  // stop(x0) >= x0
+            ends |= 1ull << e;
+            x0 = max(e, x0) + 1;
+        } while (x0 < K);
+        if (j < K) {
+            const int e = j + __ffsll(static_cast<long long>(ends >> j)) - 1;  // end of j's run
+            const uint64_t below = ends & ((1ull << j) - 1ull);
+            const int x = below ? 64 - __clzll(static_cast<long long>(below)) : 0;  // start of j's run
+            const int ox = perm[base + x];
+            const int on = perm[base + min(j + 1, K - 1)];
+            const int np = j == e ? ox : on;
+            perm[base + j] = np;
+            slot[np] = j | (r << 8);
+            if (j < K - 1 && j != e) atomicAdd(&sacc[j * R + r], 1u);
+        }
     }
 }
 
@@ -556,14 +556,16 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         for (int i = tid; i < R * 64; i += blockDim.x) stopv[i] = K - 1;
         load_xrows(xrow, tb, a.ws32, K, tid);
         if (tid < 64) {
+            // perm in LDS is set-major (slot r K + k); the buffer holds slot k R + r
+            const int src = tid < K * R ? (tid % K) * R + tid / K : tid;
             slot[tid] = 0;
-            perm[tid] = a.perm[n * 64 + tid];
+            perm[tid] = a.perm[n * 64 + src];
             sacc[tid] = a.swap_acc[n * 64 + tid];
         }
         if (tid == 0) misc[1] = a.stopped[n];
         __syncthreads();
         if (tid < K * R) {
-            const int kk = tid / R, rr = tid % R;
+            const int rr = tid / K, kk = tid - rr * K;
             slot[perm[tid]] = kk | (rr << 8);
         }
         __syncthreads();
@@ -592,9 +594,14 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         const int nt = wave < npairs ? min(iters, (npairs - wave + nwaves - 1) / nwaves) : 0;
         const cptr<uint32_t> task = ws4 + d.task_off;
         const uint32_t s_base = L.S + uint32_t(lane) * 4u;
-        const RoundKeys RK = round_keys(key0, key1);
+        // Metropolis draws: the last round's keys carry the bias kBias16 of
+        // the 16-bit comparisons, so words 0 and 2 come out biased (the exact
+        // pass removes it again)
+        RoundKeys RK = round_keys(key0, key1);
+        RK.a[9] ^= kBias16;
+        RK.b[9] ^= kBias16;
         const int tri = d.tri;
-        const uint32_t tri_m = d.tri_m, k_m = d.k_m;
+        const uint32_t tri_m = d.tri_m;
 
         for (int64_t sw = 0; sw < a.n_sweeps && !stopped; ++sw) {
             const uint32_t tt = uint32_t(t);
@@ -625,6 +632,11 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             if (nt > 0) rw_next = metro_call(ml, mu, task[(wave * 2) * iters * 8], RK);
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
+                // Fair share of the SIMD between the phase's wavefronts: each
+                // finished pair task lowers the wavefront's issue priority, so
+                // wavefronts that are behind catch up and all reach the
+                // barrier at about the same time.
+                __builtin_amdgcn_s_setprio(3);
                 for (int it = 0; it < nt; ++it) {
                     // task entry: counter word, quad indices, spin rows (scalar loads)
                     const cptr<uint32_t> te = task + ((wave * 2 + p) * iters + it) * 8;
@@ -666,8 +678,8 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         const uint32_t t1 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m1 * 32);
                         const uint32_t t2 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m2 * 32);
                         const uint32_t t3 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m3 * 32);
-                        const uint32_t u01 = (h == 0 ? rw.x : rw.z) ^ 0x80008000u;
-                        const uint32_t u23 = (h == 0 ? rw.y : rw.w) ^ 0x80008000u;
+                        const uint32_t u01 = h == 0 ? rw.x : rw.z;  // biased by the key
+                        const uint32_t u23 = (h == 0 ? rw.y : rw.w) ^ kBias16;
                         // per site d = t - u (16-bit, saturated): accept iff d > 0, tie iff d == 0
                         const uint32_t d01 = sub_sat16x2(t0 | (t1 << 16), u01);
                         const uint32_t d23 = sub_sat16x2(t2 | (t3 << 16), u23);
@@ -686,7 +698,9 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     if (__any((tmin & 0xFFFFu) == 0u || (tmin >> 16) == 0u)) {
                         // exact pass for this pair: full 32-bit uniforms
                         const MetroUniform mlo = metro_uniform(tt, kUseMetroLo, key0, key1);
-                        const uint4 rl = metro_call(ml, mlo, c1, RK);
+                        const uint4 rlb = metro_call(ml, mlo, c1, RK);
+                        const uint4 rl = make_uint4(rlb.x ^ kBias16, rlb.y, rlb.z ^ kBias16, rlb.w);
+                        const uint4 rh = make_uint4(rw.x ^ kBias16, rw.y, rw.z ^ kBias16, rw.w);
                         const uint32_t *tfull = a.ws32 + tb.tfull_off + kslot * kMRow + kMaxM;
                         e4 = e4_save;
                         nrej = nrej_save;
@@ -703,7 +717,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                             uint32_t flip = 0;
                             int ev = 0;
                             for (int k = 0; k < 4; ++k) {
-                                const uint32_t uu = (half16(rw, 4 * h + k) << 16) | half16(rl, 4 * h + k);
+                                const uint32_t uu = (half16(rh, 4 * h + k) << 16) | half16(rl, 4 * h + k);
                                 const bool acc = m[k] <= 0 || uu < tfull[m[k] >> 2];
                                 flip |= acc ? (0xFEu << (8 * k)) : 0u;
                                 ev += acc ? m[k] : -m[k];
@@ -714,17 +728,24 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     }
                     *reinterpret_cast<uint32_t *>(lds + orow[0]) = nw[0];
                     if (second) *reinterpret_cast<uint32_t *>(lds + orow[1]) = nw[1];
+                    if (it == 0)
+                        __builtin_amdgcn_s_setprio(2);
+                    else if (it == 1)
+                        __builtin_amdgcn_s_setprio(1);
+                    else
+                        __builtin_amdgcn_s_setprio(0);
                 }
-                if (p == 1 && live) atomicAdd(&Eb[lane], (e4 + int(nrej >> 3)) >> 2);
+                if (p == 1 && live) atomicAdd(&Eb[sidx], (e4 + int(nrej >> 3)) >> 2);
                 // the uniforms of a due exchange pass, drawn by the last wavefront
                 if (p == 1 && cd == 0 && wave == nwaves - 1) ux[lane] = exchange_uniform(tt, kUseSwap, K, R, key0, key1);
                 __syncthreads();
             }
-            // ---- lane energies, running minima, agreement, exchange ----
-            Ecur = Eb[lane];
-            if (__any(live && Ecur < em)) {
-                // minimum over the lane's replica set (lanes seg_lo .. seg_hi - 1)
-                int v = live ? Ecur : INT32_MAX;
+            // ---- energies, running minima, agreement, exchange ----
+            Ecur = Eb[sidx];             // this lane's configuration
+            const int Es = Eb[lane];     // slot `lane`: lanes seg_lo .. seg_hi - 1 are one set
+            if (__any(live && Es < em)) {
+                // minimum over the lane's replica set (slots seg_lo .. seg_hi - 1)
+                int v = live ? Es : INT32_MAX;
 #pragma unroll
                 for (int o = 1; o < 64; o <<= 1) {
                     const int w = __shfl(v, (lane + o) & 63, 64);
@@ -743,13 +764,11 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             const bool stop_now = stop_mode && agree && (t + 1) >= 2 * tmax;
             if (cd == 0) {
                 if (a.lds_ts_ok)
-                    exchange_stops<true>(K, R, tri, tri_m, wave, nwaves, Eb, perm, ux, xrow, stopv, tb, a.ws32,
-                                         tshi);
+                    exchange_stops<true>(K, R, tri, tri_m, wave, nwaves, Eb, ux, xrow, stopv, tb, a.ws32, tshi);
                 else
-                    exchange_stops<false>(K, R, tri, tri_m, wave, nwaves, Eb, perm, ux, xrow, stopv, tb, a.ws32,
-                                          tshi);
+                    exchange_stops<false>(K, R, tri, tri_m, wave, nwaves, Eb, ux, xrow, stopv, tb, a.ws32, tshi);
                 __syncthreads();
-                if (wave == 0) exchange_apply(K, R, k_m, perm, slot, sacc, stopv);
+                exchange_apply(K, R, wave, nwaves, perm, slot, sacc, stopv);
                 __syncthreads();
             }
             if (si > 0) cd = cd == 0 ? si - 1 : cd - 1;
@@ -774,7 +793,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             const int emh = __shfl(em, head, 64);
             const int64_t thh = __shfl(th, head, 64);
             a.energy[n * 64 + lane] = live ? Ecur : 0;
-            a.perm[n * 64 + lane] = uint8_t(perm[lane]);
+            a.perm[n * 64 + lane] = uint8_t(perm[lane < K * R ? (lane % R) * K + lane / R : lane]);
             a.swap_acc[n * 64 + lane] = sacc[lane];
             if (lane < R) {
                 a.emin[n * 64 + lane] = emh;
@@ -889,19 +908,20 @@ __global__ void __launch_bounds__(64) k_swap_extra(const InstDev *inst, const Ta
     const int n = blockIdx.x, lane = threadIdx.x;
     const InstDev d = inst[n];
     const TableDev tb = tabs[d.tab];
-    E[lane] = energy[n * 64 + lane];
-    perm[lane] = perm_g[n * 64 + lane];
+    const bool valid = lane < d.K * d.R;
+    perm[lane] = perm_g[n * 64 + (valid ? (lane % d.K) * d.R + lane / d.K : lane)];  // set-major
+    E[lane] = valid ? energy[n * 64 + perm[lane]] : 0;                                  // by slot
     sacc[lane] = swap_acc[n * 64 + lane];
     slot[lane] = 0;
     for (int i = lane; i < d.R * 64; i += 64) stopv[i] = d.K - 1;
     load_xrows(xrow, tb, ws32, d.K, lane);
     ux[lane] = exchange_uniform(uint32_t(t[n]), kUseSwapExtra, d.K, d.R, d.key0, d.key1);
     __syncthreads();
-    exchange_stops<false>(d.K, d.R, d.tri, d.tri_m, 0, 1, E, perm, ux, xrow, stopv, tb, ws32, nullptr);
+    exchange_stops<false>(d.K, d.R, d.tri, d.tri_m, 0, 1, E, ux, xrow, stopv, tb, ws32, nullptr);
     __syncthreads();
-    exchange_apply(d.K, d.R, d.k_m, perm, slot, sacc, stopv);
+    exchange_apply(d.K, d.R, 0, 1, perm, slot, sacc, stopv);
     __syncthreads();
-    perm_g[n * 64 + lane] = uint8_t(perm[lane]);
+    perm_g[n * 64 + lane] = uint8_t(perm[valid ? (lane % d.R) * d.K + lane / d.R : lane]);
     swap_acc[n * 64 + lane] = sacc[lane];
 }
 
