@@ -295,23 +295,33 @@ __device__ __forceinline__ void load_xrows(int32_t *xrow, const TableDev &tb, co
     }
 }
 
+// Test q = r T + k (k + 1) / 2 + j (T = tri = (K-1) K / 2, tri_m = ceil(2^32 / T)
+// for T >= 2) packed as r << 16 | k << 8 | j.
+__device__ __forceinline__ uint32_t exchange_test(int q, int tri, uint32_t tri_m)
+{
+    const int r = tri == 1 ? q : int(__umulhi(uint32_t(q), tri_m));
+    const int rem = q - r * tri;
+    int k = int((__fsqrt_rn(float(8 * rem + 1)) - 1.0f) * 0.5f);
+    k += ((k + 1) * (k + 2) / 2 <= rem) ? 1 : 0;
+    k -= (k * (k + 1) / 2 > rem) ? 1 : 0;
+    const int j = rem - k * (k + 1) / 2;
+    return (uint32_t(r) << 16) | (uint32_t(k) << 8) | uint32_t(j);
+}
+
+// dec0 = exchange_test(min(wave * 64 + lane, ntest - 1)), computed once per
+// instance by the caller; later rounds (more tests than lanes) decode here.
 template <bool kLds>
-__device__ void exchange_stops(int K, int R, int tri, uint32_t tri_m, int wave, int nwaves, const int32_t *Es,
-                               const uint32_t *ux, const int32_t *xrow, int32_t *stopv, const TableDev &tb,
-                               const uint32_t *ws32, const uint16_t *tshi)
+__device__ void exchange_stops(int K, int R, int tri, uint32_t tri_m, int wave, int nwaves, uint32_t dec0,
+                               const int32_t *Es, const uint32_t *ux, const int32_t *xrow, int32_t *stopv,
+                               const TableDev &tb, const uint32_t *ws32, const uint16_t *tshi)
 {
     const int lane = threadIdx.x & 63;
     const int ntest = tri * R;
     if (wave * 64 >= ntest) return;
     const uint16_t *ghi = reinterpret_cast<const uint16_t *>(ws32 + tb.ts_hi_off);
     for (int base = wave * 64; base < ntest; base += nwaves * 64) {
-        const int q = min(base + lane, ntest - 1);
-        const int r = tri == 1 ? q : int(__umulhi(uint32_t(q), tri_m));
-        const int rem = q - r * tri;
-        int k = int((__fsqrt_rn(float(8 * rem + 1)) - 1.0f) * 0.5f);
-        k += ((k + 1) * (k + 2) / 2 <= rem) ? 1 : 0;
-        k -= (k * (k + 1) / 2 > rem) ? 1 : 0;
-        const int j = rem - k * (k + 1) / 2;
+        const uint32_t dec = base == wave * 64 ? dec0 : exchange_test(min(base + lane, ntest - 1), tri, tri_m);
+        const int r = int(dec >> 16), k = int((dec >> 8) & 0xFFu), j = int(dec & 0xFFu);
         const int ex = Es[r * K + j];
         const int ey = Es[r * K + k + 1];
         const uint32_t u = ux[r * (K - 1) + k];
@@ -602,6 +612,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         RK.b[9] ^= kBias16;
         const int tri = d.tri;
         const uint32_t tri_m = d.tri_m;
+        const uint32_t xdec = exchange_test(min(tid, max(tri * R - 1, 0)), tri, tri_m);  // this lane's first test
 
         for (int64_t sw = 0; sw < a.n_sweeps && !stopped; ++sw) {
             const uint32_t tt = uint32_t(t);
@@ -764,9 +775,11 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             const bool stop_now = stop_mode && agree && (t + 1) >= 2 * tmax;
             if (cd == 0) {
                 if (a.lds_ts_ok)
-                    exchange_stops<true>(K, R, tri, tri_m, wave, nwaves, Eb, ux, xrow, stopv, tb, a.ws32, tshi);
+                    exchange_stops<true>(K, R, tri, tri_m, wave, nwaves, xdec, Eb, ux, xrow, stopv, tb, a.ws32,
+                                         tshi);
                 else
-                    exchange_stops<false>(K, R, tri, tri_m, wave, nwaves, Eb, ux, xrow, stopv, tb, a.ws32, tshi);
+                    exchange_stops<false>(K, R, tri, tri_m, wave, nwaves, xdec, Eb, ux, xrow, stopv, tb, a.ws32,
+                                          tshi);
                 __syncthreads();
                 exchange_apply(K, R, wave, nwaves, perm, slot, sacc, stopv);
                 __syncthreads();
@@ -917,7 +930,8 @@ __global__ void __launch_bounds__(64) k_swap_extra(const InstDev *inst, const Ta
     load_xrows(xrow, tb, ws32, d.K, lane);
     ux[lane] = exchange_uniform(uint32_t(t[n]), kUseSwapExtra, d.K, d.R, d.key0, d.key1);
     __syncthreads();
-    exchange_stops<false>(d.K, d.R, d.tri, d.tri_m, 0, 1, E, ux, xrow, stopv, tb, ws32, nullptr);
+    const uint32_t dec0 = exchange_test(min(lane, d.tri * d.R - 1), d.tri, d.tri_m);
+    exchange_stops<false>(d.K, d.R, d.tri, d.tri_m, 0, 1, dec0, E, ux, xrow, stopv, tb, ws32, nullptr);
     __syncthreads();
     exchange_apply(d.K, d.R, 0, 1, perm, slot, sacc, stopv);
     __syncthreads();
