@@ -196,7 +196,7 @@ __device__ __forceinline__ int wave_min(int v)
 // ---------------------------------------------------------------------------
 // Dynamic LDS layout of the sweep kernel.
 struct LdsLayout {
-    uint32_t S, ths, tshi, Eacc, perm, slot, sacc, ux, xrow, stopv, misc, total;
+    uint32_t S, ths, tshi, Eacc, perm, sacc, ux, xrow, stopv, misc, total;
 };
 
 __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int r_max)
@@ -212,9 +212,7 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int
     l.Eacc = o;
     o += 2 * 64 * 4;                              // slot energies (set-major), double-buffered by sweep parity
     l.perm = o;
-    o += 64 * 4;
-    l.slot = o;
-    o += 64 * 4;
+    o += 64 * 4;                                  // slot (set-major) -> configuration column
     l.sacc = o;
     o += 64 * 4;
     l.ux = o;
@@ -352,12 +350,11 @@ __device__ void exchange_stops(int K, int R, int tri, uint32_t tri_m, int wave, 
 // are stop(0), stop(stop(0) + 1), ... up to K - 1, found by a scalar walk
 // that reads stop(j) from lane j.  Slot k of the run [x, e] receives the
 // configuration from slot k + 1 if k < e (accepted) and the carried
-// configuration from slot x if k = e.  perm is slot -> lane (set-major),
-// slot is lane -> (k | r << 8) and sacc counts accepted exchanges by pair
-// k R + r.  Sets are disjoint, so the wavefronts of different sets touch
-// disjoint entries.
-__device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm, int32_t *slot, uint32_t *sacc,
-                               int32_t *stopv)
+// configuration from slot x if k = e.  perm maps slot (set-major) -> the
+// configuration's column and sacc counts accepted exchanges by pair k R + r.
+// Sets are disjoint, so the wavefronts of different sets touch disjoint
+// entries.
+__device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm, uint32_t *sacc, int32_t *stopv)
 {
     const int j = threadIdx.x & 63;
     for (int r = wave; r < R; r += nwaves) {
@@ -382,7 +379,6 @@ __device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm
             const int on = perm[base + min(j + 1, K - 1)];
             const int np = j == e ? ox : on;
             perm[base + j] = np;
-            slot[np] = j | (r << 8);
             if (j < K - 1 && j != e) atomicAdd(&sacc[j * R + r], 1u);
         }
     }
@@ -508,7 +504,6 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
     uint16_t *THS = reinterpret_cast<uint16_t *>(lds + L.ths);
     int32_t *Eacc = reinterpret_cast<int32_t *>(lds + L.Eacc);
     int32_t *perm = reinterpret_cast<int32_t *>(lds + L.perm);
-    int32_t *slot = reinterpret_cast<int32_t *>(lds + L.slot);
     uint32_t *sacc = reinterpret_cast<uint32_t *>(lds + L.sacc);
     uint32_t *ux = reinterpret_cast<uint32_t *>(lds + L.ux);
     int32_t *xrow = reinterpret_cast<int32_t *>(lds + L.xrow);
@@ -568,21 +563,31 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         if (tid < 64) {
             // perm in LDS is set-major (slot r K + k); the buffer holds slot k R + r
             const int src = tid < K * R ? (tid % K) * R + tid / K : tid;
-            slot[tid] = 0;
             perm[tid] = a.perm[n * 64 + src];
             sacc[tid] = a.swap_acc[n * 64 + tid];
         }
         if (tid == 0) misc[1] = a.stopped[n];
         __syncthreads();
-        if (tid < K * R) {
-            const int rr = tid / K, kk = tid - rr * K;
-            slot[perm[tid]] = kk | (rr << 8);
-        }
-        __syncthreads();
 
-        // per-lane state every wavefront keeps (identical in all of them)
+        // Lane l is slot l = r K + k (temperature k of replica set r) in every
+        // wavefront; the configuration it updates is spin column perm[l],
+        // which changes only in exchange passes.  Dead lanes keep their own
+        // (unused) column.
         const bool live = lane < nlanes;
-        int Ecur = live ? a.energy[n * 64 + lane] : 0;
+        const int kslot = live ? lane % K : 0;
+        const uint32_t sword = live ? (uint32_t(kslot) << 8) | uint32_t(lane / K) : 0u;
+        // threshold column of this lane's temperature, entry m at byte m * 128
+        const uint32_t thl_base = L.ths + uint32_t(kMaxM) * 128u + uint32_t(lane) * 2u;
+        MetroLane ml;
+        {
+            uint32_t h, l;
+            mul_hilo(sword, M1, h, l);
+            ml.a = h ^ key0;
+            ml.lo = l;
+        }
+        int col = live ? perm[lane] : lane;
+        int Es = live ? a.energy[n * 64 + col] : 0;  // energy of slot `lane` after the last sweep
+        int col_e = col;                              // the column Es belongs to
         const int set = live ? lane / K : 0;
         const int seg_lo = set * K, seg_hi = seg_lo + K;
         int em = a.emin[n * 64 + set];
@@ -603,7 +608,6 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         // pair tasks of this wavefront per phase: it = 0 .. nt-1 with wave + it nwaves < npairs
         const int nt = wave < npairs ? min(iters, (npairs - wave + nwaves - 1) / nwaves) : 0;
         const cptr<uint32_t> task = ws4 + d.task_off;
-        const uint32_t s_base = L.S + uint32_t(lane) * 4u;
         // Metropolis draws: the last round's keys carry the bias kBias16 of
         // the 16-bit comparisons, so words 0 and 2 come out biased (the exact
         // pass removes it again)
@@ -614,33 +618,24 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         const uint32_t tri_m = d.tri_m;
         const uint32_t xdec = exchange_test(min(tid, max(tri * R - 1, 0)), tri, tri_m);  // this lane's first test
 
+        // The Philox draw of the next task (the next pair of this phase, the
+        // first pair of phase 1, or the first pair of the next sweep) is
+        // computed while the spin rows of the current task are being read;
+        // the draws do not depend on the exchange passes, since a lane's slot
+        // is fixed.
+        uint4 rw_next = make_uint4(0u, 0u, 0u, 0u);
+        if (nt > 0) rw_next = metro_call(ml, metro_uniform(uint32_t(t), kUseMetroHi, key0, key1),
+                                         task[(wave * 2) * iters * 8], RK);
+
         for (int64_t sw = 0; sw < a.n_sweeps && !stopped; ++sw) {
             const uint32_t tt = uint32_t(t);
-            // per-lane slot state (changes only in exchange passes)
-            const int sl = slot[lane];
-            const int kslot = min(sl & 0xFF, K - 1);
-            const uint32_t sidx = live ? uint32_t((sl >> 8) * K + kslot) : uint32_t(lane);
-            const uint32_t sword = (uint32_t(sl & 0xFF) << 8) | uint32_t(sl >> 8);
-            // threshold column of this lane's slot, entry m at byte m * 128
-            const uint32_t thl_base = L.ths + uint32_t(kMaxM) * 128u + sidx * 2u;
-            MetroLane ml;
-            {
-                uint32_t h, l;
-                mul_hilo(sword, M1, h, l);
-                ml.a = h ^ key0;
-                ml.lo = l;
-            }
+            const uint32_t s_base = L.S + uint32_t(col) * 4u;
             const MetroUniform mu = metro_uniform(tt, kUseMetroHi, key0, key1);
+            const MetroUniform mu_next = metro_uniform(tt + 1u, kUseMetroHi, key0, key1);
             int32_t *Eb = Eacc + (tt & 1u) * 64u;
             if (wave == 0) Eb[lane] = 0;
             int e4 = 0;        // phase 1: sum of (m4 ^ s) over this wavefront's sites
             uint32_t nrej = 0; // phase 1: 8 x rejected sites
-
-            // The Philox draw of the next task (the next pair of this phase, or
-            // the first pair of phase 1) is computed while the spin rows of the
-            // current task are being read.
-            uint4 rw_next = make_uint4(0u, 0u, 0u, 0u);
-            if (nt > 0) rw_next = metro_call(ml, mu, task[(wave * 2) * iters * 8], RK);
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
                 // Fair share of the SIMD between the phase's wavefronts: each
@@ -665,9 +660,10 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         B[h] = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab >> 16) << 8));
                     }
                     const uint4 rw = rw_next;
-                    if (it + 1 < nt || p == 0) {
-                        const uint32_t c1n = it + 1 < nt ? te[8] : task[((wave * 2 + 1) * iters) * 8];
-                        rw_next = metro_call(ml, mu, c1n, RK);
+                    {
+                        const bool last = it + 1 == nt;
+                        const uint32_t c1n = !last ? te[8] : task[((wave * 2 + 1 - p) * iters) * 8];
+                        rw_next = metro_call(ml, (p == 1 && last) ? mu_next : mu, c1n, RK);
                     }
                     uint32_t nw[2];
                     const int e4_save = e4;
@@ -746,14 +742,14 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     else
                         __builtin_amdgcn_s_setprio(0);
                 }
-                if (p == 1 && live) atomicAdd(&Eb[sidx], (e4 + int(nrej >> 3)) >> 2);
+                if (p == 1 && live) atomicAdd(&Eb[lane], (e4 + int(nrej >> 3)) >> 2);
                 // the uniforms of a due exchange pass, drawn by the last wavefront
                 if (p == 1 && cd == 0 && wave == nwaves - 1) ux[lane] = exchange_uniform(tt, kUseSwap, K, R, key0, key1);
                 __syncthreads();
             }
             // ---- energies, running minima, agreement, exchange ----
-            Ecur = Eb[sidx];             // this lane's configuration
-            const int Es = Eb[lane];     // slot `lane`: lanes seg_lo .. seg_hi - 1 are one set
+            Es = Eb[lane];  // slot `lane`: lanes seg_lo .. seg_hi - 1 are one set
+            col_e = col;
             if (__any(live && Es < em)) {
                 // minimum over the lane's replica set (slots seg_lo .. seg_hi - 1)
                 int v = live ? Es : INT32_MAX;
@@ -781,8 +777,9 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     exchange_stops<false>(K, R, tri, tri_m, wave, nwaves, xdec, Eb, ux, xrow, stopv, tb, a.ws32,
                                           tshi);
                 __syncthreads();
-                exchange_apply(K, R, wave, nwaves, perm, slot, sacc, stopv);
+                exchange_apply(K, R, wave, nwaves, perm, sacc, stopv);
                 __syncthreads();
+                col = live ? perm[lane] : lane;
             }
             if (si > 0) cd = cd == 0 ? si - 1 : cd - 1;
             stopped = stop_now;
@@ -805,7 +802,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             const int head = min(lane, R - 1) * K;
             const int emh = __shfl(em, head, 64);
             const int64_t thh = __shfl(th, head, 64);
-            a.energy[n * 64 + lane] = live ? Ecur : 0;
+            a.energy[n * 64 + (live ? col_e : lane)] = live ? Es : 0;
             a.perm[n * 64 + lane] = uint8_t(perm[lane < K * R ? (lane % R) * K + lane / R : lane]);
             a.swap_acc[n * 64 + lane] = sacc[lane];
             if (lane < R) {
@@ -916,7 +913,7 @@ __global__ void __launch_bounds__(64) k_swap_extra(const InstDev *inst, const Ta
                                                    const int32_t *energy, uint32_t *swap_acc,
                                                    const int64_t *t)
 {
-    __shared__ int32_t E[64], perm[64], slot[64], xrow[128], stopv[64 * 64];
+    __shared__ int32_t E[64], perm[64], xrow[128], stopv[64 * 64];
     __shared__ uint32_t sacc[64], ux[64];
     const int n = blockIdx.x, lane = threadIdx.x;
     const InstDev d = inst[n];
@@ -925,7 +922,6 @@ __global__ void __launch_bounds__(64) k_swap_extra(const InstDev *inst, const Ta
     perm[lane] = perm_g[n * 64 + (valid ? (lane % d.K) * d.R + lane / d.K : lane)];  // set-major
     E[lane] = valid ? energy[n * 64 + perm[lane]] : 0;                                  // by slot
     sacc[lane] = swap_acc[n * 64 + lane];
-    slot[lane] = 0;
     for (int i = lane; i < d.R * 64; i += 64) stopv[i] = d.K - 1;
     load_xrows(xrow, tb, ws32, d.K, lane);
     ux[lane] = exchange_uniform(uint32_t(t[n]), kUseSwapExtra, d.K, d.R, d.key0, d.key1);
@@ -933,7 +929,7 @@ __global__ void __launch_bounds__(64) k_swap_extra(const InstDev *inst, const Ta
     const uint32_t dec0 = exchange_test(min(lane, d.tri * d.R - 1), d.tri, d.tri_m);
     exchange_stops<false>(d.K, d.R, d.tri, d.tri_m, 0, 1, dec0, E, ux, xrow, stopv, tb, ws32, nullptr);
     __syncthreads();
-    exchange_apply(d.K, d.R, 0, 1, perm, slot, sacc, stopv);
+    exchange_apply(d.K, d.R, 0, 1, perm, sacc, stopv);
     __syncthreads();
     perm_g[n * 64 + lane] = uint8_t(perm[valid ? (lane % d.R) * d.K + lane / d.R : lane]);
     swap_acc[n * 64 + lane] = sacc[lane];
