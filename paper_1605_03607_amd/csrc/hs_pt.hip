@@ -206,7 +206,7 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int
     l.S = o;
     o += (uint32_t(ncell_max) * 2 + 1) * 64 * 4;  // spin rows, then one zero row
     l.ths = o;
-    o += uint32_t(kMRow) * 64 * 2;                // 16-bit threshold columns by slot index
+    o += uint32_t(kMRow) * 64 * 4;                // 16-bit thresholds in 4-byte columns by slot
     l.tshi = o;
     o += ((uint32_t(tshi_max) * 2 + 15) / 16) * 16;
     l.Eacc = o;
@@ -551,7 +551,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             const uint32_t th = a.ws32[tb.thi_off + k * kMRow + m];
             // 0x10000 ("always", m <= 0) becomes 0xFFFF: a uniform of 0xFFFF then
             // ties and the exact pass accepts
-            THS[i] = uint16_t((th >= 0x10000u ? 0xFFFFu : th) ^ 0x8000u);
+            THS[2 * i] = uint16_t((th >= 0x10000u ? 0xFFFFu : th) ^ 0x8000u);
         }
         if (a.lds_ts_ok) {
             const uint32_t *src = a.ws32 + tb.ts_hi_off;
@@ -576,8 +576,9 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         const bool live = lane < nlanes;
         const int kslot = live ? lane % K : 0;
         const uint32_t sword = live ? (uint32_t(kslot) << 8) | uint32_t(lane / K) : 0u;
-        // threshold column of this lane's temperature, entry m at byte m * 128
-        const uint32_t thl_base = L.ths + uint32_t(kMaxM) * 128u + uint32_t(lane) * 2u;
+        // threshold column of this lane's temperature, entry m at byte m * 256
+        // (4-byte column stride: every lane of a gather reads its own bank)
+        const uint32_t thl_base = L.ths + uint32_t(kMaxM) * 256u + uint32_t(lane) * 4u;
         MetroLane ml;
         {
             uint32_t h, l;
@@ -680,11 +681,11 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         const int m1 = site_m4<1>(o0[h], oth[h], x01, jq[1], jq[5]);
                         const int m2 = site_m4<2>(o0[h], oth[h], x23, jq[2], jq[6]);
                         const int m3 = site_m4<3>(o0[h], oth[h], x23, jq[3], jq[7]);
-                        // sign-flipped 16-bit thresholds of the four sites (m4 * 32 = m * 128 bytes)
-                        const uint32_t t0 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m0 * 32);
-                        const uint32_t t1 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m1 * 32);
-                        const uint32_t t2 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m2 * 32);
-                        const uint32_t t3 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m3 * 32);
+                        // sign-flipped 16-bit thresholds of the four sites (m4 * 64 = m * 256 bytes)
+                        const uint32_t t0 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m0 * 64);
+                        const uint32_t t1 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m1 * 64);
+                        const uint32_t t2 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m2 * 64);
+                        const uint32_t t3 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m3 * 64);
                         const uint32_t u01 = h == 0 ? rw.x : rw.z;  // biased by the key
                         const uint32_t u23 = (h == 0 ? rw.y : rw.w) ^ kBias16;
                         // per site d = t - u (16-bit, saturated): accept iff d > 0, tie iff d == 0
