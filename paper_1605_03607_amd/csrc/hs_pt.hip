@@ -619,14 +619,19 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         const uint32_t tri_m = d.tri_m;
         const uint32_t xdec = exchange_test(min(tid, max(tri * R - 1, 0)), tri, tri_m);  // this lane's first test
 
-        // The Philox draw of the next task (the next pair of this phase, the
-        // first pair of phase 1, or the first pair of the next sweep) is
-        // computed while the spin rows of the current task are being read;
-        // the draws do not depend on the exchange passes, since a lane's slot
-        // is fixed.
-        uint4 rw_next = make_uint4(0u, 0u, 0u, 0u);
-        if (nt > 0) rw_next = metro_call(ml, metro_uniform(uint32_t(t), kUseMetroHi, key0, key1),
-                                         task[(wave * 2) * iters * 8], RK);
+        // Philox draws do not depend on the exchange passes, since a lane's
+        // slot is fixed.  The draws of the first two pairs of phase 0 are made
+        // ahead (pre0, pre1), during the previous sweep's exchange pass by the
+        // wavefronts that do not walk the runs; every other draw (the next
+        // pair of the phase, or the first pair of phase 1) is computed while
+        // the spin rows of the current pair are being read.
+        const int nwalk = min(R, nwaves);  // wavefronts of the exchange walk
+        uint4 pre0 = make_uint4(0u, 0u, 0u, 0u), pre1 = pre0;
+        auto predraw = [&](const MetroUniform &m) {
+            if (nt > 0) pre0 = metro_call(ml, m, task[(wave * 2) * iters * 8], RK);
+            if (nt > 1) pre1 = metro_call(ml, m, task[((wave * 2) * iters + 1) * 8], RK);
+        };
+        predraw(metro_uniform(uint32_t(t), kUseMetroHi, key0, key1));
 
         for (int64_t sw = 0; sw < a.n_sweeps && !stopped; ++sw) {
             const uint32_t tt = uint32_t(t);
@@ -637,6 +642,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             if (wave == 0) Eb[lane] = 0;
             int e4 = 0;        // phase 1: sum of (m4 ^ s) over this wavefront's sites
             uint32_t nrej = 0; // phase 1: 8 x rejected sites
+            uint4 rw_next = pre0;
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
                 // Fair share of the SIMD between the phase's wavefronts: each
@@ -663,8 +669,12 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     const uint4 rw = rw_next;
                     {
                         const bool last = it + 1 == nt;
-                        const uint32_t c1n = !last ? te[8] : task[((wave * 2 + 1 - p) * iters) * 8];
-                        rw_next = metro_call(ml, (p == 1 && last) ? mu_next : mu, c1n, RK);
+                        if (p == 0 && it == 0 && !last) {
+                            rw_next = pre1;
+                        } else if (p == 0 || !last) {
+                            const uint32_t c1n = !last ? te[8] : task[((wave * 2 + 1) * iters) * 8];
+                            rw_next = metro_call(ml, mu, c1n, RK);
+                        }
                     }
                     uint32_t nw[2];
                     const int e4_save = e4;
@@ -778,9 +788,13 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     exchange_stops<false>(K, R, tri, tri_m, wave, nwaves, xdec, Eb, ux, xrow, stopv, tb, a.ws32,
                                           tshi);
                 __syncthreads();
+                if (wave >= nwalk) predraw(mu_next);
                 exchange_apply(K, R, wave, nwaves, perm, sacc, stopv);
                 __syncthreads();
+                if (wave < nwalk) predraw(mu_next);
                 col = live ? perm[lane] : lane;
+            } else {
+                predraw(mu_next);
             }
             if (si > 0) cd = cd == 0 ? si - 1 : cd - 1;
             stopped = stop_now;
