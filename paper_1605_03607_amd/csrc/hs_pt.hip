@@ -199,14 +199,15 @@ struct LdsLayout {
     uint32_t S, ths, tshi, Eacc, perm, sacc, ux, xrow, stopv, misc, total;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int r_max)
+// mode 1: 2-byte threshold columns (else 4-byte: no two lanes share a bank).
+__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int r_max, int mode)
 {
     LdsLayout l;
     uint32_t o = 0;
     l.S = o;
     o += (uint32_t(ncell_max) * 2 + 1) * 64 * 4;  // spin rows, then one zero row
     l.ths = o;
-    o += uint32_t(kMRow) * 64 * 4;                // 16-bit thresholds in 4-byte columns by slot
+    o += uint32_t(kMRow) * 64 * ((mode & 1) ? 2 : 4);  // 16-bit thresholds, one column per slot
     l.tshi = o;
     o += ((uint32_t(tshi_max) * 2 + 15) / 16) * 16;
     l.Eacc = o;
@@ -247,6 +248,7 @@ struct SweepArgs {
     uint32_t flags;
     int32_t ncell_max, tshi_max, r_max;
     int32_t lds_ts_ok;        // 1 if every ladder's fast exchange table fits in LDS
+    int32_t lds_mode;         // lds_layout mode
 };
 
 // Exchange decisions (detailed balance, Sec. II) for configuration x at
@@ -495,7 +497,8 @@ __device__ __forceinline__ int site_m4(uint32_t own, uint32_t oth, uint32_t xv, 
 __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
 {
     extern __shared__ __align__(16) char lds[];
-    const LdsLayout L = lds_layout(a.ncell_max, a.tshi_max, a.r_max);
+    const LdsLayout L = lds_layout(a.ncell_max, a.tshi_max, a.r_max, a.lds_mode);
+    const uint32_t ths_sh = (a.lds_mode & 1) ? 5u : 6u;  // entry m of a column at byte (4 m) << ths_sh
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -551,7 +554,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             const uint32_t th = a.ws32[tb.thi_off + k * kMRow + m];
             // 0x10000 ("always", m <= 0) becomes 0xFFFF: a uniform of 0xFFFF then
             // ties and the exact pass accepts
-            THS[2 * i] = uint16_t((th >= 0x10000u ? 0xFFFFu : th) ^ 0x8000u);
+            THS[(uint32_t(i) << ths_sh) >> 5] = uint16_t((th >= 0x10000u ? 0xFFFFu : th) ^ 0x8000u);
         }
         if (a.lds_ts_ok) {
             const uint32_t *src = a.ws32 + tb.ts_hi_off;
@@ -576,9 +579,9 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         const bool live = lane < nlanes;
         const int kslot = live ? lane % K : 0;
         const uint32_t sword = live ? (uint32_t(kslot) << 8) | uint32_t(lane / K) : 0u;
-        // threshold column of this lane's temperature, entry m at byte m * 256
-        // (4-byte column stride: every lane of a gather reads its own bank)
-        const uint32_t thl_base = L.ths + uint32_t(kMaxM) * 256u + uint32_t(lane) * 4u;
+        // threshold column of this lane's temperature
+        // (with 4-byte columns every lane of a gather reads its own bank)
+        const uint32_t thl_base = L.ths + ((uint32_t(kMaxM) * 4u) << ths_sh) + ((uint32_t(lane) << ths_sh) >> 4);
         MetroLane ml;
         {
             uint32_t h, l;
@@ -622,7 +625,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         // Philox draws do not depend on the exchange passes, since a lane's
         // slot is fixed.  The draws of the first two pairs of phase 0 are made
         // ahead (pre0, pre1), during the previous sweep's exchange pass by the
-        // wavefronts that do not walk the runs; every other draw (the next
+        // wavefronts that do not walk the runs.  Every other draw (the next
         // pair of the phase, or the first pair of phase 1) is computed while
         // the spin rows of the current pair are being read.
         const int nwalk = min(R, nwaves);  // wavefronts of the exchange walk
@@ -691,11 +694,11 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         const int m1 = site_m4<1>(o0[h], oth[h], x01, jq[1], jq[5]);
                         const int m2 = site_m4<2>(o0[h], oth[h], x23, jq[2], jq[6]);
                         const int m3 = site_m4<3>(o0[h], oth[h], x23, jq[3], jq[7]);
-                        // sign-flipped 16-bit thresholds of the four sites (m4 * 64 = m * 256 bytes)
-                        const uint32_t t0 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m0 * 64);
-                        const uint32_t t1 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m1 * 64);
-                        const uint32_t t2 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m2 * 64);
-                        const uint32_t t3 = *reinterpret_cast<const uint16_t *>(lds + thl_base + m3 * 64);
+                        // sign-flipped 16-bit thresholds of the four sites
+                        const uint32_t t0 = *reinterpret_cast<const uint16_t *>(lds + thl_base + (uint32_t(m0) << ths_sh));
+                        const uint32_t t1 = *reinterpret_cast<const uint16_t *>(lds + thl_base + (uint32_t(m1) << ths_sh));
+                        const uint32_t t2 = *reinterpret_cast<const uint16_t *>(lds + thl_base + (uint32_t(m2) << ths_sh));
+                        const uint32_t t3 = *reinterpret_cast<const uint16_t *>(lds + thl_base + (uint32_t(m3) << ths_sh));
                         const uint32_t u01 = h == 0 ? rw.x : rw.z;  // biased by the key
                         const uint32_t u23 = (h == 0 ? rw.y : rw.w) ^ kBias16;
                         // per site d = t - u (16-bit, saturated): accept iff d > 0, tie iff d == 0
@@ -967,6 +970,7 @@ struct hs_pt {
     int grid = 0;
     int ncell_max = 0, tshi_max = 0, r_max = 1;
     int lds_ts_ok = 1;
+    int lds_mode = 0;
     size_t lds_bytes = 0;
     // workspace layout (byte offsets)
     size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0;
@@ -990,6 +994,7 @@ struct Plan {
     size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0;
     int ncell_max = 0, K_max = 0, tshi_max = 0, r_max = 1;
     int lds_ts_ok = 1;
+    int lds_mode = 0;
     size_t total_words = 0;
 };
 
@@ -1152,14 +1157,31 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
         x.ts_full_row_off = int64_t(append(img, h.ts_full_row.data(), h.ts_full_row.size()));
         P.tshi_max = std::max(P.tshi_max, int(h.ts_hi.size()));
     }
-    if (size_t(P.tshi_max) * 2 > kLdsTsBudget ||
-        dev::lds_layout(P.ncell_max, P.tshi_max, P.r_max).total > kLdsLimit) {
-        P.lds_ts_ok = 0;
-        P.tshi_max = 0;
-    }
-    if (dev::lds_layout(P.ncell_max, 0, P.r_max).total > kLdsLimit) {
-        err = "instance too large for one workgroup's LDS";
-        return HS_EUNSUPPORTED;
+    // LDS layout: the fast exchange table in LDS first, then 4-byte threshold
+    // columns, whichever fit
+    {
+        const int modes[2] = {0, 1};
+        bool found = false;
+        if (size_t(P.tshi_max) * 2 <= kLdsTsBudget) {
+            for (int m : modes)
+                if (!found && dev::lds_layout(P.ncell_max, P.tshi_max, P.r_max, m).total <= kLdsLimit) {
+                    P.lds_mode = m;
+                    found = true;
+                }
+        }
+        if (!found) {
+            P.lds_ts_ok = 0;
+            P.tshi_max = 0;
+            for (int m : modes)
+                if (!found && dev::lds_layout(P.ncell_max, 0, P.r_max, m).total <= kLdsLimit) {
+                    P.lds_mode = m;
+                    found = true;
+                }
+        }
+        if (!found) {
+            err = "instance too large for one workgroup's LDS";
+            return HS_EUNSUPPORTED;
+        }
     }
     // order: most expensive first
     P.order.resize(n);
@@ -1237,11 +1259,12 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
     h->tshi_max = P.tshi_max;
     h->r_max = P.r_max;
     h->lds_ts_ok = P.lds_ts_ok;
+    h->lds_mode = P.lds_mode;
     h->off_inst = P.off_inst;
     h->off_tabs = P.off_tabs;
     h->off_order = P.off_order;
     h->off_queue = P.off_queue;
-    h->lds_bytes = dev::lds_layout(h->ncell_max, h->tshi_max, h->r_max).total;
+    h->lds_bytes = dev::lds_layout(h->ncell_max, h->tshi_max, h->r_max, h->lds_mode).total;
     h->host_ws = std::move(P.image);
     if (h->n_inst == 0) {
         *out = h;
@@ -1321,6 +1344,7 @@ int sweep_launch(hs_pt *h, int64_t n_sweeps, hipStream_t stream)
     a.tshi_max = h->tshi_max;
     a.r_max = h->r_max;
     a.lds_ts_ok = h->lds_ts_ok;
+    a.lds_mode = h->lds_mode;
     hipLaunchKernelGGL(dev::k_reset_queue, dim3(1), dim3(1), 0, stream, a.queue);
     hipLaunchKernelGGL(dev::k_pt_sweep, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, stream, a);
     hipError_t e = hipGetLastError();

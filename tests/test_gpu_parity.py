@@ -237,3 +237,23 @@ def test_full_size_c8_batch_sampled(swap_interval):
         o = _oracle_run(insts[n], cfg["seed"], swap_interval, n_sweeps)
         _assert_same(b.state(n), o, f"instance {n}")
     b.close()
+
+
+@pytest.mark.parametrize("K,R", [(32, 2), (64, 1), (1, 64), (2, 32)])
+def test_largest_lattice_parity(K, R):
+    """C16 (the largest lattice the engine takes, N = 2048) with 2% missing
+    spins and 64 lanes: the launch picks the most compact LDS layout that
+    fits (the largest R needs the most room for run ends), and every shape
+    matches the oracle."""
+    hs = _gpu()
+    L = 16
+    d = dict(L=L, J=workloads.couplings(L, "pm7", 21, K), live=workloads.missing_mask(L, 0.02, 21, K),
+             K=K, R=R, beta=workloads.geometric_betas(0.1, 5.0, K),
+             instance_id=77)
+    _say(f"C16 parity: K={K} R={R}")
+    b = hs.PTBatch([d], SEED, swap_interval=1)
+    b.sweep(30)
+    o = _oracle_run(d, SEED, 1, 30)
+    _assert_same(b.state(0), o, f"C16 K={K} R={R}")
+    assert b.measure() == 0
+    b.close()
