@@ -350,7 +350,7 @@ __device__ void exchange_stops(int K, int R, int tri, uint32_t tri_m, int wave, 
 
 // Step 2 (wavefront r mod nwaves for set r, lane j): the run ends of set r
 // are stop(0), stop(stop(0) + 1), ... up to K - 1, found by a scalar walk
-// that reads stop(j) from lane j.  Slot k of the run [x, e] receives the
+// that reads stop(j) from lane j, two runs per step.  Slot k of the run [x, e] receives the
 // configuration from slot k + 1 if k < e (accepted) and the carried
 // configuration from slot x if k = e.  perm maps slot (set-major) -> the
 // configuration's column and sacc counts accepted exchanges by pair k R + r.
@@ -366,12 +366,16 @@ __device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm
             st = stopv[r * 64 + j];
             stopv[r * 64 + j] = K - 1;  // ready for the next pass
         }
+        // two runs per step: st2(j) = stop(stop(j) + 1) ends the run after j's
+        // (K - 1 when j's run is the last)
+        const int st2 = __shfl(st, min(st + 1, K - 1), 64);
         uint64_t ends = 0;
         int x0 = 0;
         do {
-            const int e = __builtin_amdgcn_readlane(st, x0);  // stop(x0) >= x0
-            ends |= 1ull << e;
-            x0 = max(e, x0) + 1;
+            const int e1 = __builtin_amdgcn_readlane(st, x0);  // stop(x0) >= x0
+            const int e2 = __builtin_amdgcn_readlane(st2, x0);
+            ends |= (1ull << e1) | (1ull << e2);
+            x0 = max(e2, x0) + 1;
         } while (x0 < K);
         if (j < K) {
             const int e = j + __ffsll(static_cast<long long>(ends >> j)) - 1;  // end of j's run
