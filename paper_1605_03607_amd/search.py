@@ -35,7 +35,7 @@ def _geometric(lo, hi, k):
 class SearchConfig:
     def __init__(self, mode="plain", chains=64, L=8, restarts=32, K=32, R=2, beta=(0.1, 5.0),
                  swap_interval=1, s_max=100_000, t_s=0.5, seed=1605, proposals=16, top=2,
-                 train_steps=4, train_batch=16, lr=1e-3, replay=4096, screen_chunk=128):
+                 train_steps=32, train_batch=32, lr=3e-3, replay=4096, screen_chunk=128):
         self.mode = mode
         self.chains, self.L, self.restarts, self.K, self.R = chains, L, restarts, K, R
         self.beta = _geometric(beta[0], beta[1], K)
