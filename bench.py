@@ -40,9 +40,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pt_sweep_c8x256_traffic.json")
 
 
 def kernel_fingerprint():
+    """Hash of the sweep-kernel source without comments and blank lines, so
+    that edits of comments alone keep the committed counters valid."""
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    import re
+    with open(KERNEL_SOURCE) as f:
+        src = f.read()
+    token = re.compile(r'"(?:\\.|[^"\\])*"|//[^\n]*|/\*.*?\*/', re.S)
+    code = token.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", src)
+    lines = [" ".join(l.split()) for l in code.splitlines()]
+    return hashlib.sha256("\n".join(l for l in lines if l).encode()).hexdigest()[:16]
 
 
 def measured_traffic():

@@ -13,7 +13,7 @@
  *     (r,c,1,k)-(r,c+1,1,k) between cells.  Canonical coupler order:
  *     ascending (min id, max id); the full C_L has 24 L^2 - 8 L couplers.
  *   - A spin bit b = 1 means s = -1.  Spins are exchanged "word-major": one
- *     uint64 per site, bit l = the spin bit of replica lane l.
+ *     uint64 per site, bit l = the spin bit of replica configuration l.
  *   - Lanes, slots: an instance runs K temperatures x R replica sets
  *     (K R <= 64 lanes).  Lane r K + k starts at temperature slot (k, r);
  *     exchanges move configurations between slots of the same replica set

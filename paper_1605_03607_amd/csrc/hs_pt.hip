@@ -1,9 +1,12 @@
 // gfx950 kernels and C ABI of the parallel-tempering engine (libhardspin).
 //
 // Layout on the device (one workgroup per instance, persistent work queue):
-//   * Spins live in LDS "lane-major": one thread = one replica lane, and the
-//     four spins of one side of one K_{4,4} cell are the four bytes of one
-//     dword (byte = +1 or -1, i.e. 0x01 / 0xFF).  S[cell][side][lane].
+//   * Spins live in LDS in 64 columns, one per replica configuration, and
+//     the four spins of one side of one K_{4,4} cell are the four bytes of
+//     one dword (byte = +1 or -1, i.e. 0x01 / 0xFF).  S[cell][side][column].
+//     Lane l of every wavefront is slot l = r K + k (temperature k of replica
+//     set r) for the whole launch and updates column perm[l], the
+//     configuration currently at that temperature.
 //   * The local field of a site is two v_dot4_i32_i8: the four spins of the
 //     opposite side of the cell times four coupling bytes, plus the two
 //     inter-cell neighbours (v_perm'd into one dword) times two coupling
@@ -15,15 +18,14 @@
 //     halves come from a second Philox use and are computed only when a lane
 //     ties on the high half (probability 2^-16 per attempt).
 //   * Thresholds: fast table thi[k][m] = T >> 16 (0x10000 for m <= 0), held
-//     in LDS as one column per slot (k, r), column r K + k.  A lane's column
-//     moves with its slot; the columns of the 64 lanes are a permutation that
-//     keeps each replica set in its own block, so the per-lane gather is free
-//     of bank conflicts and the table never changes.  The exact table
+//     in LDS as one column per slot (lane), biased by 0x8000 so that packed
+//     signed 16-bit arithmetic compares it with the uniforms; with 4-byte
+//     columns the per-lane gather is free of bank conflicts.  The exact table
 //     T = floor(2^32 exp(-2 beta m)) stays in global memory for ties.
 //   * Exchange passes: every wavefront evaluates part of the acceptance tests
 //     of pair (k, k+1) for every configuration that can be carried into slot
 //     k, then one wavefront per replica set links the runs of accepted
-//     exchanges.
+//     exchanges and rewrites perm.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -495,7 +497,7 @@ __device__ __forceinline__ int site_m4(uint32_t own, uint32_t oth, uint32_t xv, 
 // joins a colour-0 and a colour-1 site, so the energy after the sweep is
 // sum over colour-1 sites of s_i' h_i (Eq. 1), with h_i the local field seen
 // in phase 1 and s_i' the spin after its update: phase 1 alone yields the
-// lane energies, accumulated in LDS with atomics.  Every wavefront then keeps
+// slot energies, accumulated in LDS with atomics.  Every wavefront then keeps
 // its own copy of the running minima (identical in all wavefronts) and, when
 // an exchange pass is due, the two exchange steps add two barriers.
 __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)

@@ -62,13 +62,14 @@ def _blocks(theta):
     return out
 
 
-@pytest.mark.parametrize("L,n,missing", [(3, 5, 0.05), (8, 16, 0.0)])
+@pytest.mark.parametrize("L,n,missing", [(3, 5, 0.05), (8, 16, 0.0), (1, 2, 0.0), (16, 2, 0.02)])
 def test_forward_and_gradients_match_oracle(L, n, missing):
     hs = _gpu()
     gr = _graphs(L, n, 17, missing)
     theta = _theta()
     labels = np.linspace(-1.0, 2.0, n)
-    labels[1] = np.inf  # an unlabelled graph is left out of the loss
+    if n > 2:
+        labels[1] = np.inf  # an unlabelled graph is left out of the loss
     sur = hs.Surrogate(theta)
     sur.prepare(gr)
     y = sur.forward()
@@ -78,12 +79,17 @@ def test_forward_and_gradients_match_oracle(L, n, missing):
     l64, g64, y64 = G.loss_and_grad(theta.astype(np.float64), B, labels)
     lbf, gbf, ybf = G.loss_and_grad(theta.astype(np.float64), B, labels, bf=True)
     assert np.array_equal(y, y2)
-    assert _rel(y, y64) < 2e-2
+    # a C1 graph has 8 nodes: the readout mean and the 4-neighbour message
+    # sums average too few terms to damp the BF16 roundings (2^-9 relative,
+    # about seven per path), so against float64 it gets 5e-2; the BF16-rounding
+    # oracle keeps the 1e-3 bound at every size
+    tol64 = 2e-2 if L >= 2 else 5e-2
+    assert _rel(y, y64) < tol64
     assert _rel(y, ybf) < 1e-3, _rel(y, ybf)
     assert abs(loss - lbf) <= 1e-3 * abs(lbf)
     b_gpu, b64, bbf = _blocks(grad), _blocks(g64), _blocks(gbf)
     for name in b_gpu:
-        assert _rel(b_gpu[name], b64[name]) < 2e-2, (name, _rel(b_gpu[name], b64[name]))
+        assert _rel(b_gpu[name], b64[name]) < tol64, (name, _rel(b_gpu[name], b64[name]))
         assert _rel(b_gpu[name], bbf[name]) < 1e-3, (name, _rel(b_gpu[name], bbf[name]))
 
 
