@@ -79,7 +79,7 @@ def parse():
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed steps, run one plain device copy of this many MiB "
                         "(reference kernel for scaling HBM byte counters)")
-    p.add_argument("--workload", choices=["c8", "uneven", "search", "surrogate"], default="c8",
+    p.add_argument("--workload", choices=["c8", "uneven", "search", "search-reverse", "surrogate"], default="c8",
                    help="c8: the 256 x C8 batch (default); uneven: 1024 instances C4..C12, "
                         "autotuned shape, HIP-graph replay, live attempts/s; search: bounded "
                         "plain / surrogate-screened / random-screened instance search")
@@ -244,6 +244,43 @@ def search(args):
     print(json.dumps(out), flush=True)
 
 
+def search_reverse(args):
+    """The reversed search (Sec. II.B): plain chains that favour shorter TTS,
+    from the same +-1 seeds with sign-flip mutations (Algorithm 1's move);
+    easy instances per hour and the drop of the median ln TTS (the paper
+    lowers TTS about tenfold below random instances)."""
+    import math
+
+    from paper_1605_03607_amd import search as S
+    seeds = workloads.search_seeds(args.search_chains)
+    bars = {"ln3": math.log(3.0), "ln10": math.log(10.0)}
+    cfg = S.SearchConfig(mode="plain", chains=args.search_chains, direction=-1, alphabet=S.ALPHABET_PM1)
+    run = S.Search(cfg, seeds)
+    h0 = run.h0
+    t0 = time.perf_counter()
+    for k in range(args.search_steps):
+        run.run_step(bars=tuple(bars.values()))
+        print(f"# reverse: step {k + 1}/{args.search_steps}", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    easy = {name: len(run.hard.get(b, set())) for name, b in bars.items()}
+    med = float(np.median(run.ln))
+    out = {
+        "metric": "easy instances/hour (reversed search)",
+        "value": easy["ln3"] / (wall / 3600.0),
+        "unit": "easy instances/hour (ln TTS <= H0 - ln 3)",
+        "n_gpus": 1, "steps": args.search_steps, "warmup": 0,
+        "ms_per_step": wall * 1e3 / args.search_steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32 (PT)", "data": "synthetic",
+        "config": {"workload": f"reversed instance search, {args.search_chains} C8 chains, +-1 seeds, "
+                               "sign-flip mutations (J stays +-1), 32 restarts K32 R2, T_s 0.5",
+                   "bounded_steps": args.search_steps},
+        "easy_instances": easy, "h0_ln_tts": h0, "final_median_ln_tts": med,
+        "median_drop_ln": h0 - med, "accepted": run.accepted, "pt_sweeps": int(run.pt_sweeps),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def surrogate(args):
     """Surrogate step times on C8 graphs: a training step (forward, backward,
     Adam) on the 16-graph batch and the forward pass that screens 1024
@@ -294,6 +331,9 @@ def main():
         sys.exit(2)
     if args.workload == "uneven":
         uneven(args)
+        return
+    if args.workload == "search-reverse":
+        search_reverse(args)
         return
     if args.workload == "search":
         search(args)

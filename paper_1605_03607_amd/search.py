@@ -1,9 +1,11 @@
 """Instance-space search driven by the gfx950 engine (Algorithm 1, Sec. II.A).
 
 Every chain holds one instance J.  A step proposes coupler mutations
-(instance_mutate), scores candidates with hardness_eval (ln of the median
-time-to-solution over independent PT restarts, in sweeps) and accepts by
-Metropolis in ln TTS at search temperature t_s (hs_rao_accept).  Three modes:
+(instance_mutate over `alphabet`: +-1..+-7 by default, +-1 for Algorithm 1's
+sign flips), scores candidates with hardness_eval (ln of the PT run time per
+find of the ground state over independent restarts, in sweeps; Appendix B)
+and accepts by Metropolis in ln TTS at search temperature t_s
+(hs_rao_accept).  Three modes:
 
   plain      one proposal per chain, scored by PT (Algorithm 1 as written)
   surrogate  `proposals` mutations per chain ranked by the surrogate network;
@@ -16,6 +18,13 @@ Metropolis in ln TTS at search temperature t_s (hs_rao_accept).  Three modes:
 PT stays the judge of every accepted instance.  A hard instance is an
 accepted state with ln TTS >= H0 + ln(bar), H0 = median ln TTS of the seed
 instances; distinct hard instances are counted by their couplings.
+
+direction = -1 is the reversed search of Sec. II.B: the acceptance test runs
+on -ln TTS (shorter times are favoured), the screen keeps the proposals with
+the lowest predicted ln TTS, the better of the PT-scored candidates is the
+one with the lower ln TTS, and the counted states are the easy ones,
+ln TTS <= H0 - ln(bar).  Every acceptance decision is logged in `decisions`
+as (step, chain, ln_cur, ln_new, w, accepted).
 """
 import hashlib
 import math
@@ -26,6 +35,7 @@ import numpy as np
 from . import Surrogate, gnn_fan_ins, hardness_eval, instance_mutate, rao_accept
 
 ALPHABET_PM7 = np.array([-7, -6, -5, -4, -3, -2, -1, 1, 2, 3, 4, 5, 6, 7], np.int8)
+ALPHABET_PM1 = np.array([-1, 1], np.int8)  # Algorithm 1's sign flips
 
 
 def _geometric(lo, hi, k):
@@ -35,8 +45,13 @@ def _geometric(lo, hi, k):
 class SearchConfig:
     def __init__(self, mode="plain", chains=64, L=8, restarts=32, K=32, R=2, beta=(0.1, 5.0),
                  swap_interval=1, s_max=100_000, t_s=0.5, seed=1605, proposals=16, top=2,
-                 train_steps=32, train_batch=32, lr=3e-3, replay=4096, screen_chunk=128):
+                 train_steps=32, train_batch=32, lr=3e-3, replay=4096, screen_chunk=128, direction=1,
+                 alphabet=ALPHABET_PM7):
+        if direction not in (1, -1):
+            raise ValueError("direction is +1 (harder) or -1 (easier)")
         self.mode = mode
+        self.direction = direction
+        self.alphabet = np.ascontiguousarray(alphabet, np.int8)
         self.chains, self.L, self.restarts, self.K, self.R = chains, L, restarts, K, R
         self.beta = _geometric(beta[0], beta[1], K)
         self.swap_interval, self.s_max, self.t_s, self.seed = swap_interval, s_max, t_s, seed
@@ -67,6 +82,7 @@ class Search:
         self.h0 = float(np.median(self.ln))
         self.accepted = 0
         self.hard = {}
+        self.decisions = []
 
     def _score(self, cands):
         c = self.cfg
@@ -87,7 +103,7 @@ class Search:
         c = self.cfg
         out = []
         for p in range(c.proposals):
-            e, old, new, w = instance_mutate(dict(L=c.L, J=self.J[chain], live=None), ALPHABET_PM7, chain,
+            e, old, new, w = instance_mutate(dict(L=c.L, J=self.J[chain], live=None), c.alphabet, chain,
                                              c.seed, self.step, p)
             J2 = self.J[chain].copy()
             J2[e] = new
@@ -122,7 +138,7 @@ class Search:
         if c.mode == "plain":
             chosen = [[0] for _ in range(c.chains)]
         elif c.mode == "surrogate":
-            pred = self._rank(props)
+            pred = self._rank(props) * c.direction
             chosen = [sorted(np.argsort(-pred[ch], kind="stable")[:c.top].tolist()) for ch in range(c.chains)]
         else:
             chosen = [sorted(self.rng.choice(c.proposals, size=c.top, replace=False).tolist())
@@ -135,18 +151,21 @@ class Search:
                 owner.append((ch, p))
         ln = self._score(cands)
         best = {}
+        d = c.direction
         for (ch, p), y in zip(owner, ln):
-            if ch not in best or y > best[ch][1]:  # ties keep the lower proposal index
+            if ch not in best or d * y > d * best[ch][1]:  # ties keep the lower proposal index
                 best[ch] = (p, y)
         for ch in range(c.chains):
             p, y = best[ch]
             J2, w, _ = props[ch][p]
-            if rao_accept(self.ln[ch], y, c.t_s, w):
+            ok = rao_accept(d * self.ln[ch], d * y, c.t_s, w)
+            self.decisions.append((self.step, ch, float(self.ln[ch]), float(y), int(w), bool(ok)))
+            if ok:
                 self.J[ch] = J2
                 self.ln[ch] = y
                 self.accepted += 1
                 for b in bars:
-                    if y >= self.h0 + b:
+                    if d * (y - self.h0) >= b:
                         self.hard.setdefault(b, set()).add(_key(J2))
         self._train()
         self.step += 1
