@@ -142,6 +142,15 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
  * by agreement, Appendix B).  Asynchronous. */
 int pt_sweep(hs_pt *h, int64_t n_sweeps);
 
+/* pt_sweep that also records the temperature random walk (Sec. III.B): after
+ * the e-th exchange pass of this call (e < capacity), walk[(n capacity + e)
+ * 64 + c] = temperature index k of configuration c of instance n (c < K R;
+ * bytes of c >= K R and of passes not made are left untouched).  walk is a
+ * caller-owned device buffer of n_inst x capacity x 64 bytes.  Results are
+ * identical to pt_sweep's.  HS_EINVAL for capacity < 0 or a NULL walk with
+ * capacity > 0.  Asynchronous. */
+int pt_sweep_record(hs_pt *h, int64_t n_sweeps, uint8_t *walk, int64_t capacity);
+
 /* HIP graph of a sweep launch.  pt_graph_create captures the launches that
  * pt_sweep(h, n_sweeps) would enqueue (a work-queue reset and one persistent
  * sweep kernel) on a private capture stream and instantiates them;

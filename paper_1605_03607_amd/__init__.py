@@ -90,6 +90,11 @@ def lib():
         L.pt_init.argtypes = [C.POINTER(C.c_void_p), C.POINTER(hs_pt_desc), C.POINTER(hs_buffers),
                               C.c_void_p]
         L.pt_sweep.argtypes = [C.c_void_p, C.c_int64]
+        L.pt_sweep_record.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]
+        L.walk_autocorr.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]
+        L.walk_tau.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_double, C.POINTER(C.c_double),
+                               C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.pt_swap.argtypes = [C.c_void_p]
         L.pt_measure.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
         L.pt_destroy.argtypes = [C.c_void_p]
@@ -144,7 +149,7 @@ def exported_symbols():
             "pt_measure", "pt_destroy", "pt_graph_create", "pt_graph_launch", "pt_graph_destroy",
             "pt_autotune", "instance_mutate", "hs_rao_accept", "hardness_workspace_bytes",
             "hardness_eval", "gnn_param_count", "gnn_workspace_bytes", "gnn_prepare", "gnn_forward",
-            "gnn_train_step"]
+            "gnn_train_step", "pt_sweep_record", "walk_autocorr", "walk_tau"]
 
 
 def _check(rc):
@@ -216,6 +221,16 @@ class PTBatch:
 
     def sweep(self, n_sweeps):
         _check(lib().pt_sweep(self.h, int(n_sweeps)))
+
+    def sweep_record(self, n_sweeps, walk):
+        """pt_sweep that writes the temperature walk into `walk` (a uint8
+        device tensor [n_inst, capacity, 64]): entry [n, e, c] = temperature
+        index of configuration c after the e-th exchange pass of this call."""
+        torch = _torch()
+        if walk.dtype != torch.uint8 or walk.dim() != 3 or walk.shape[0] < max(1, self.n) or \
+                walk.shape[2] != 64 or not walk.is_contiguous() or not walk.is_cuda:
+            raise ValueError("walk must be a contiguous CUDA uint8 tensor [n_inst, capacity, 64]")
+        _check(lib().pt_sweep_record(self.h, int(n_sweeps), C.c_void_p(walk.data_ptr()), int(walk.shape[1])))
 
     def graph(self, n_sweeps):
         """A captured HIP graph whose replay runs n_sweeps more sweeps."""
@@ -364,6 +379,31 @@ def hardness_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed, blo
                     n_censored=det[i].n_censored, sweeps_total=det[i].sweeps_total)
                for i in range(len(cands))]
     return ln, details
+
+
+# ---------------------------------------------------------------------------
+# Mixing time of the temperature walk (include/hs_walk.h).
+def walk_autocorr(walk, n_steps, K, R, max_lag, stream=None):
+    """Exact autocorrelation sums S(d) (int64 [n_inst, max_lag + 1]) and
+    hot-half passes (int64 [n_inst, 64]) of a walk tensor written by
+    PTBatch.sweep_record; returned as numpy arrays."""
+    torch = _torch()
+    n_inst, cap = int(walk.shape[0]), int(walk.shape[1])
+    acf = torch.zeros((max(1, n_inst), max_lag + 1), dtype=torch.int64, device=walk.device)
+    hot = torch.zeros((max(1, n_inst), 64), dtype=torch.int64, device=walk.device)
+    _check(lib().walk_autocorr(C.c_void_p(walk.data_ptr()), n_inst, cap, int(n_steps), int(K), int(R),
+                               int(max_lag), C.c_void_p(acf.data_ptr()), C.c_void_p(hot.data_ptr()),
+                               _stream_ptr(stream)))
+    return acf.cpu().numpy()[:n_inst], hot.cpu().numpy()[:n_inst]
+
+
+def walk_tau(acf_row, n_steps, c_window=6.0):
+    """(tau in exchange passes, window, converged) from one row of S(d)."""
+    a = np.ascontiguousarray(acf_row, np.int64)
+    tau, win, conv = C.c_double(0), C.c_int(0), C.c_int(0)
+    _check(lib().walk_tau(a.ctypes.data, len(a) - 1, int(n_steps), float(c_window), C.byref(tau), C.byref(win),
+                          C.byref(conv)))
+    return tau.value, win.value, bool(conv.value)
 
 
 # ---------------------------------------------------------------------------

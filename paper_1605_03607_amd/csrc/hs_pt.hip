@@ -251,6 +251,8 @@ struct SweepArgs {
     int32_t ncell_max, tshi_max, r_max;
     int32_t lds_ts_ok;        // 1 if every ladder's fast exchange table fits in LDS
     int32_t lds_mode;         // lds_layout mode
+    uint8_t *walk;            // optional: temperature index per configuration after each exchange pass
+    int64_t walk_cap;         // exchange passes the walk buffer holds per instance
 };
 
 // Exchange decisions (detailed balance, Sec. II) for configuration x at
@@ -641,6 +643,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             if (nt > 1) pre1 = metro_call(ml, m, task[((wave * 2) * iters + 1) * 8], RK);
         };
         predraw(metro_uniform(uint32_t(t), kUseMetroHi, key0, key1));
+        int64_t n_ex = 0;  // exchange passes made in this launch
 
         for (int64_t sw = 0; sw < a.n_sweeps && !stopped; ++sw) {
             const uint32_t tt = uint32_t(t);
@@ -802,6 +805,10 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                 __syncthreads();
                 if (wave < nwalk) predraw(mu_next);
                 col = live ? perm[lane] : lane;
+                // temperature walk: configuration col now sits at temperature kslot
+                if (a.walk != nullptr && wave == nwaves - 1 && n_ex < a.walk_cap && live)
+                    a.walk[(int64_t(n) * a.walk_cap + n_ex) * 64 + col] = uint8_t(kslot);
+                ++n_ex;
             } else {
                 predraw(mu_next);
             }
@@ -1325,7 +1332,8 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
 namespace {
 
 // Enqueues the work-queue reset and the persistent sweep kernel on `stream`.
-int sweep_launch(hs_pt *h, int64_t n_sweeps, hipStream_t stream)
+int sweep_launch(hs_pt *h, int64_t n_sweeps, hipStream_t stream, uint8_t *walk = nullptr,
+                 int64_t walk_cap = 0)
 {
     char *ws = reinterpret_cast<char *>(h->buf.workspace);
     dev::SweepArgs a;
@@ -1351,6 +1359,8 @@ int sweep_launch(hs_pt *h, int64_t n_sweeps, hipStream_t stream)
     a.r_max = h->r_max;
     a.lds_ts_ok = h->lds_ts_ok;
     a.lds_mode = h->lds_mode;
+    a.walk = walk;
+    a.walk_cap = walk_cap;
     hipLaunchKernelGGL(dev::k_reset_queue, dim3(1), dim3(1), 0, stream, a.queue);
     hipLaunchKernelGGL(dev::k_pt_sweep, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, stream, a);
     hipError_t e = hipGetLastError();
@@ -1373,6 +1383,14 @@ int pt_sweep(hs_pt *h, int64_t n_sweeps)
     if (h == nullptr || n_sweeps < 0) return fail(HS_EINVAL, "pt_sweep: bad arguments");
     if (h->n_inst == 0 || n_sweeps == 0) return HS_OK;
     return sweep_launch(h, n_sweeps, h->stream);
+}
+
+int pt_sweep_record(hs_pt *h, int64_t n_sweeps, uint8_t *walk, int64_t capacity)
+{
+    if (h == nullptr || n_sweeps < 0 || capacity < 0 || (walk == nullptr && capacity > 0))
+        return fail(HS_EINVAL, "pt_sweep_record: bad arguments");
+    if (h->n_inst == 0 || n_sweeps == 0) return HS_OK;
+    return sweep_launch(h, n_sweeps, h->stream, walk, capacity);
 }
 
 int pt_graph_create(hs_pt *h, int64_t n_sweeps, hs_graph **out)

@@ -15,6 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "hardspin.h")
 GNN_HEADER = os.path.join(ROOT, "include", "hs_gnn.h")
 PROBE_HEADER = os.path.join(ROOT, "include", "hs_probe.h")
+WALK_HEADER = os.path.join(ROOT, "include", "hs_walk.h")
 
 
 def _hs():
@@ -44,7 +45,8 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", hs.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
     exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
-    declared = _declared_functions() + _declared_functions(GNN_HEADER)
+    declared = _declared_functions() + _declared_functions(GNN_HEADER) + _declared_functions(WALK_HEADER)
+    assert {"pt_sweep_record", "walk_autocorr", "walk_tau"} <= set(declared)
     missing = [n for n in declared if n not in exported]
     assert not missing, missing
     lib = hs.lib()
@@ -149,3 +151,38 @@ def test_workspace_grows_with_batch():
         assert hs.lib().pt_workspace_bytes(C.byref(desc), C.byref(nb)) == 0
         sizes.append(nb.value)
     assert sizes[0] < sizes[1] < sizes[2]
+
+
+def test_walk_tau_matches_oracle():
+    """The library's window rule and tau against the oracle's, on the sums
+    of a seeded two-state chain, of independent draws and of a short run."""
+    import oracle.walk as W
+    hs = _hs()
+    rng = np.random.default_rng(8)
+    cases = []
+    for p, T in ((0.05, 50_000), (0.3, 20_000), (0.5, 3)):
+        st = np.cumsum(rng.random(T) < p) % 2
+        cases.append((W.acf_sums(st[:, None], 2, 200), T))
+    cases.append((W.acf_sums(rng.integers(0, 6, size=(5000, 4)), 6, 40), 5000))
+    cases.append((np.zeros(5, np.int64), 100))
+    for S, T in cases:
+        got = hs.walk_tau(S, T)
+        want = W.tau_int(S, T)
+        assert got[1:] == tuple(want[1:])
+        assert abs(got[0] - want[0]) <= 1e-12 * max(1.0, abs(want[0]))
+
+
+def test_walk_entry_points_reject_bad_sizes():
+    hs = _hs()
+    import ctypes as C
+    lib = hs.lib()
+    acf = np.zeros(4, np.int64)
+    tau, win, conv = C.c_double(), C.c_int(), C.c_int()
+    assert lib.walk_tau(None, 3, 10, 6.0, C.byref(tau), C.byref(win), C.byref(conv)) == -1
+    assert lib.walk_tau(acf.ctypes.data, -1, 10, 6.0, C.byref(tau), C.byref(win), C.byref(conv)) == -1
+    for args in ((0, 4, 5, 8, 2, 10), (0, 4, 2, 0, 2, 10), (0, 4, 2, 8, 9, 10), (0, 4, 2, 8, 2, -1),
+                 (-1, 4, 2, 8, 2, 10)):
+        n, cap, T, K, R, lag = args
+        assert lib.walk_autocorr(None, n, cap, T, K, R, lag, None, None, None) == -1, args
+    assert lib.walk_autocorr(None, 0, 4, 2, 8, 2, 10, None, None, None) == 0
+    assert lib.pt_sweep_record(None, 10, None, 0) == -1
