@@ -79,12 +79,14 @@ def parse():
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed steps, run one plain device copy of this many MiB "
                         "(reference kernel for scaling HBM byte counters)")
-    p.add_argument("--workload", choices=["c8", "uneven", "search", "search-reverse", "surrogate"], default="c8",
+    p.add_argument("--workload", choices=["c8", "uneven", "search", "search-reverse", "surrogate", "tau"],
+                   default="c8",
                    help="c8: the 256 x C8 batch (default); uneven: 1024 instances C4..C12, "
                         "autotuned shape, HIP-graph replay, live attempts/s; search: bounded "
                         "plain / surrogate-screened / random-screened instance search")
     p.add_argument("--search-steps", type=int, default=20)
     p.add_argument("--search-chains", type=int, default=64)
+    p.add_argument("--tau-emcs", type=int, default=20000, help="EMCS of the --workload tau run")
     p.add_argument("--probe", action="store_true",
                    help="also measure instruction issue rates (libhsprobe.so)")
     return p.parse_args()
@@ -281,6 +283,63 @@ def search_reverse(args):
     print(json.dumps(out), flush=True)
 
 
+def tau(args):
+    """Mixing time of the temperature random walk (Sec. III.B) for 256 C8
+    instances with +-1 couplings: K = 32 temperatures (beta 0.1..5.0) x R = 2
+    chains, EMCS = 10 sweeps + one exchange pass, a bounded run of
+    --tau-emcs EMCS recorded on the device, then exact autocorrelation sums,
+    the automatic-window tau and the paper's two acceptance criteria."""
+    import torch
+
+    import paper_1605_03607_amd as hs
+    n_inst, K, R, si = 256, 32, 2, 10
+    T = args.tau_emcs
+    max_lag = min(65535, max(1, T // 4))
+    beta = workloads.geometric_betas(0.1, 5.0, K)
+    insts = [dict(L=8, J=workloads.couplings(8, "pm1", 2024, n), live=None, K=K, R=R, beta=beta,
+                  instance_id=n) for n in range(n_inst)]
+    b = hs.PTBatch(insts, 2024, swap_interval=si)
+    walk = torch.zeros((n_inst, T, 64), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    b.sweep_record(T * si, walk)
+    e1.record(stream)
+    acf, hot = hs.walk_autocorr(walk, T, K, R, max_lag)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_pt, ms_acf = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    taus, ok_i, ok_ii, conv = [], 0, 0, 0
+    for n in range(n_inst):
+        t_emcs, win, c = hs.walk_tau(acf[n], T)
+        share = float(hot[n, :K * R].min()) / T
+        taus.append(t_emcs * si)
+        ok_i += share >= 0.2
+        ok_ii += T >= 20 * t_emcs
+        conv += c
+    attempts = n_inst * K * R * 512 * T * si
+    out = {
+        "metric": "mixing time of the temperature walk (instances per hour)",
+        "value": n_inst / (wall / 3600.0),
+        "unit": "instances with tau estimated per hour (bounded run)",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32 (PT) / int64 (sums)", "data": "synthetic",
+        "config": {"workload": f"tau, {n_inst} C8 instances J=+-1, K{K} R{R} beta 0.1..5.0, EMCS = {si} sweeps + "
+                               f"1 exchange, {T} EMCS", "max_lag_emcs": max_lag},
+        "pt_attempts_per_s": attempts / (ms_pt / 1e3), "pt_ms": ms_pt, "acf_ms": ms_acf,
+        "tau_sweeps": {"median": float(np.median(taus)), "p90": float(np.percentile(taus, 90)),
+                       "max": float(np.max(taus))},
+        "window_converged": int(conv), "criterion_hot_half": int(ok_i), "criterion_20_tau": int(ok_ii),
+        "energy_mismatches": b.measure(),
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def surrogate(args):
     """Surrogate step times on C8 graphs: a training step (forward, backward,
     Adam) on the 16-graph batch and the forward pass that screens 1024
@@ -331,6 +390,9 @@ def main():
         sys.exit(2)
     if args.workload == "uneven":
         uneven(args)
+        return
+    if args.workload == "tau":
+        tau(args)
         return
     if args.workload == "search-reverse":
         search_reverse(args)
