@@ -209,6 +209,52 @@ int instance_mutate(const hs_instance *in, const int8_t *alphabet, int n_alpha, 
  * infinite new value is accepted; inf - inf counts as 0), else 0. */
 int hs_rao_accept(double ln_cur, double ln_new, double t_s, uint32_t w);
 
+/* Planted-solution instances and the moves of Loop Adaptive Optimization
+ * (Sec. IV, Algorithm 2).  An instance is a sum of n_loops frustrated loop
+ * Hamiltonians on simple cycles of 4 or 6 couplers of the live Chimera graph;
+ * each loop's couplings keep the planted state s* among its ground states,
+ * so s* is a ground state of the sum and E_gs = sum over loops of
+ * -(size - 2) weight.
+ *   - Loop (size, cycle, weight, flip): cycle indexes the cycles of that
+ *     size, each identified by its ascending coupler indices and the list
+ *     sorted by them; weight in 1..5; on every coupler but the flip-th (in
+ *     ascending order) J += -weight s*_i s*_j, on that one J += +weight
+ *     s*_i s*_j (Fig. 6: integer weights 1..5, 4-cycles with probability
+ *     0.1, else 6-cycles).
+ *   - A loop that would push a coupler past |J| = 7 (the engine's range) is
+ *     drawn again with the next attempt counter, at most 64 times
+ *     (HS_EUNSUPPORTED after that).
+ *   - Draws: planted bit i = bit 31 of word 0 of Philox((chain, seed),
+ *     (i, 0, 1, 8)) (0 for missing sites).  Initial loop m, attempt a: words
+ *     (w0, w1, w2, w3) of Philox((chain, seed), (m, a, 0, 8)): size 4 iff
+ *     w0 < 429496730, cycle floor(w1 n / 2^32), weight 1 + floor(w2 5 / 2^32),
+ *     flip floor(w3 size / 2^32).  Move (step, proposal): Philox((chain,
+ *     seed), (step, proposal, 0, 9)) gives the removed loop floor(w0 n_loops
+ *     / 2^32) and the acceptance uniform w1; the new loop comes from
+ *     Philox((chain, seed), (step, proposal, 1 + a, 9)) as above.
+ * J arrays hold every canonical coupler (24 L^2 - 8 L bytes); planted holds
+ * one bit per site.  Host only; the cycle lists are built once per (L, live)
+ * and cached.  HS_EINVAL for bad arguments or an invalid loop. */
+typedef struct hs_loop {
+    int32_t size;   /* 4 or 6 */
+    int32_t cycle;  /* index among the cycles of that size */
+    int32_t weight; /* 1..5 */
+    int32_t flip;   /* the unsatisfied coupler's position, 0..size-1 */
+} hs_loop;
+int lao_cycle_count(int L, const uint8_t *live, int size, int64_t *count);
+int lao_init(int L, const uint8_t *live, int n_loops, uint32_t chain, uint32_t seed, hs_loop *loops,
+             uint8_t *planted, int8_t *J, int64_t *e_gs);
+/* The proposal (step, proposal) for an instance: *slot = the loop removed,
+ * *new_loop = its replacement, J_new / *e_gs_new = the candidate's couplings
+ * and planted ground-state energy, *w_accept = the uniform for hs_rao_accept.
+ * The candidate must fit |J| <= 7 everywhere (removing a loop can push a
+ * shared coupler past it); when no attempt does, the proposal is void:
+ * *slot = -1 and J_new / *e_gs_new repeat the instance's.  The instance is
+ * not modified. */
+int lao_move(int L, const uint8_t *live, int n_loops, uint32_t chain, uint32_t seed, uint32_t step,
+             uint32_t proposal, const hs_loop *loops, const uint8_t *planted, int32_t *slot, hs_loop *new_loop,
+             uint32_t *w_accept, int8_t *J_new, int64_t *e_gs_new);
+
 /* Hardness of candidate instances: n_restarts independent PT runs per
  * candidate (restart rho keyed by (word 0 of Philox((instance_id, seed),
  * (rho, 0, 0, 5)), seed)), each until replica agreement or s_max sweeps

@@ -16,7 +16,11 @@ open or gives them only for its figure):
     the loop's ascending coupler order (J += +w s_i s_j), so s* pays
     -(n - 2) w on an n-loop, the loop minimum;
   * the engine takes |J| <= 7: a loop that would push a coupler past 7 is
-    drawn again (next attempt counter), up to MAX_ATTEMPTS times;
+    drawn again (next attempt counter), up to MAX_ATTEMPTS times.  Removing
+    a loop can itself push a coupler past 7 (loops of opposite signs
+    sharing it); a move is kept only if the whole new instance is within
+    the cap, and a proposal with no such attempt is void (slot -1: the
+    instance stays, as a rejected move);
   * a cycle is identified by its ascending tuple of canonical coupler
     indices; the candidates of one size are ordered by that tuple;
   * draws: planted bit i = bit 31 of word 0 of Philox((chain, seed),
@@ -134,7 +138,8 @@ def init(L, n_loops, chain, seed, live=None, cyc=None):
 
 
 def move(L, inst, chain, seed, step, proposal, live=None, cyc=None):
-    """(slot, new loop, w_accept, J' (int8), e_gs') of a proposal."""
+    """(slot, new loop, w_accept, J' (int8), e_gs') of a proposal; slot -1
+    (and the instance's own J, e_gs) when no attempt fits the cap."""
     cyc = cyc or cycles(L, live)
     M = len(inst["loops"])
     w = philox((step, proposal, 0, D_MOVE), (chain, seed))
@@ -144,9 +149,11 @@ def move(L, inst, chain, seed, step, proposal, live=None, cyc=None):
     for a in range(MAX_ATTEMPTS):
         lp = _loop_from_words(philox((step, proposal, 1 + a, D_MOVE), (chain, seed)), cyc)
         idx, d = loop_couplings(L, lp, cyc, inst["bits"])
-        if _fits(J, idx, d):
+        J_try = J.copy()
+        J_try[idx] += d
+        if np.all(np.abs(J_try) <= J_CAP):
             loops = list(inst["loops"])
             loops[slot] = lp
             J2, e_gs = couplings(L, loops, cyc, inst["bits"])
             return slot, lp, int(w[1]), J2.astype(np.int8), e_gs
-    raise ValueError("loop does not fit under the coupling cap")
+    return -1, None, int(w[1]), np.asarray(inst["J"], np.int8), inst["e_gs"]

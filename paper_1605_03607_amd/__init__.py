@@ -93,6 +93,12 @@ def lib():
         L.pt_sweep_record.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]
         L.walk_autocorr.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
+        L.lao_cycle_count.argtypes = [C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_int64)]
+        L.lao_init.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.POINTER(C.c_int64)]
+        L.lao_move.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                               C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p, C.POINTER(C.c_uint32),
+                               C.c_void_p, C.POINTER(C.c_int64)]
         L.walk_tau.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_double, C.POINTER(C.c_double),
                                C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.pt_swap.argtypes = [C.c_void_p]
@@ -149,7 +155,8 @@ def exported_symbols():
             "pt_measure", "pt_destroy", "pt_graph_create", "pt_graph_launch", "pt_graph_destroy",
             "pt_autotune", "instance_mutate", "hs_rao_accept", "hardness_workspace_bytes",
             "hardness_eval", "gnn_param_count", "gnn_workspace_bytes", "gnn_prepare", "gnn_forward",
-            "gnn_train_step", "pt_sweep_record", "walk_autocorr", "walk_tau"]
+            "gnn_train_step", "pt_sweep_record", "walk_autocorr", "walk_tau", "lao_cycle_count", "lao_init",
+            "lao_move"]
 
 
 def _check(rc):
@@ -379,6 +386,53 @@ def hardness_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed, blo
                     n_censored=det[i].n_censored, sweeps_total=det[i].sweeps_total)
                for i in range(len(cands))]
     return ln, details
+
+
+# ---------------------------------------------------------------------------
+# Planted-solution instances and LAO moves (hardspin.h).
+def _n_couplers(L):
+    return 24 * L * L - 8 * L
+
+
+def _live_arg(live):
+    if live is None:
+        return None, None
+    a = np.ascontiguousarray(live, np.uint8)
+    return a, C.c_void_p(a.ctypes.data)
+
+
+def lao_cycle_count(L, size, live=None):
+    keep, lp = _live_arg(live)
+    n = C.c_int64(0)
+    _check(lib().lao_cycle_count(int(L), lp, int(size), C.byref(n)))
+    return n.value
+
+
+def lao_init(L, n_loops, chain, seed, live=None):
+    """Planted instance: dict(loops int32 [n_loops, 4] = (size, cycle,
+    weight, flip), bits uint8 [N], J int8, e_gs)."""
+    keep, lp = _live_arg(live)
+    loops = np.zeros((n_loops, 4), np.int32)
+    bits = np.zeros(8 * L * L, np.uint8)
+    J = np.zeros(_n_couplers(L), np.int8)
+    e = C.c_int64(0)
+    _check(lib().lao_init(int(L), lp, int(n_loops), int(chain), int(seed), loops.ctypes.data, bits.ctypes.data,
+                          J.ctypes.data, C.byref(e)))
+    return dict(loops=loops, bits=bits, J=J, e_gs=e.value)
+
+
+def lao_move(L, inst, chain, seed, step, proposal, live=None):
+    """(slot, new loop (size, cycle, weight, flip), w_accept, J', e_gs')."""
+    keep, lp = _live_arg(live)
+    loops = np.ascontiguousarray(inst["loops"], np.int32)
+    bits = np.ascontiguousarray(inst["bits"], np.uint8)
+    slot, w = C.c_int32(0), C.c_uint32(0)
+    new = np.zeros(4, np.int32)
+    J = np.zeros(_n_couplers(L), np.int8)
+    e = C.c_int64(0)
+    _check(lib().lao_move(int(L), lp, len(loops), int(chain), int(seed), int(step), int(proposal), loops.ctypes.data,
+                          bits.ctypes.data, C.byref(slot), new.ctypes.data, C.byref(w), J.ctypes.data, C.byref(e)))
+    return slot.value, tuple(int(x) for x in new), w.value, J, e.value
 
 
 # ---------------------------------------------------------------------------

@@ -170,3 +170,67 @@ class Search:
         self._train()
         self.step += 1
 
+
+
+class LaoSearch:
+    """Loop Adaptive Optimization (Sec. IV, Algorithm 2) on planted-solution
+    instances: every chain starts from lao_init's instance of n_loops
+    frustrated loops; a step replaces one loop (lao_move), scores the
+    candidate with hardness_eval and accepts by Metropolis in ln TTS
+    (hs_rao_accept).  The planted ground-state energy travels with the
+    instance; `gs_found` counts scored candidates whose PT ground state
+    (minimum over restarts) reached it, `voids` counts proposals with no
+    replacement loop under the coupling cap (kept as rejected moves), and
+    `decisions` logs (step, chain, ln_cur, ln_new, w, accepted)."""
+
+    def __init__(self, cfg, n_loops, seed_chain0=0):
+        from . import lao_init
+        self.cfg = cfg
+        self.n_loops = n_loops
+        self.inst = [lao_init(cfg.L, n_loops, seed_chain0 + ch, cfg.seed) for ch in range(cfg.chains)]
+        self.chain_id = [seed_chain0 + ch for ch in range(cfg.chains)]
+        self.step = 0
+        self.pt_seconds = 0.0
+        self.pt_sweeps = 0
+        self.scored = 0
+        self.gs_found = 0
+        self.accepted = 0
+        self.voids = 0
+        self.decisions = []
+        self.ln = self._score([(ch, i["J"], i["e_gs"]) for ch, i in enumerate(self.inst)])
+        self.ln0 = self.ln.copy()
+
+    def _score(self, cands):
+        c = self.cfg
+        t0 = time.perf_counter()
+        ln, det = hardness_eval([dict(L=c.L, J=J, live=None, instance_id=self.chain_id[ch]) for ch, J, _ in cands],
+                                c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
+        self.pt_seconds += time.perf_counter() - t0
+        self.pt_sweeps += sum(d["sweeps_total"] for d in det)
+        for (_, _, e_gs), d in zip(cands, det):
+            self.scored += 1
+            self.gs_found += int(d["e_gs"] == e_gs)
+        return np.asarray(ln, np.float64)
+
+    def run_step(self):
+        from . import lao_move
+        c = self.cfg
+        moves = [lao_move(c.L, self.inst[ch], self.chain_id[ch], c.seed, self.step, 0) for ch in range(c.chains)]
+        live = [ch for ch, m in enumerate(moves) if m[0] >= 0]  # void proposals are rejected moves
+        scores = self._score([(ch, moves[ch][3], moves[ch][4]) for ch in live]) if live else []
+        ln = dict(zip(live, scores))
+        for ch, (slot, lp, w, J2, e2) in enumerate(moves):
+            if slot < 0:
+                self.voids += 1
+                continue
+            ok = rao_accept(self.ln[ch], ln[ch], c.t_s, w)
+            self.decisions.append((self.step, ch, float(self.ln[ch]), float(ln[ch]), int(w), bool(ok)))
+            if ok:
+                inst = self.inst[ch]
+                inst["loops"] = inst["loops"].copy()
+                inst["loops"][slot] = lp
+                inst["J"] = J2
+                inst["e_gs"] = e2
+                self.ln[ch] = ln[ch]
+                self.accepted += 1
+        self.step += 1

@@ -186,3 +186,71 @@ def test_walk_entry_points_reject_bad_sizes():
         assert lib.walk_autocorr(None, n, cap, T, K, R, lag, None, None, None) == -1, args
     assert lib.walk_autocorr(None, 0, 4, 2, 8, 2, 10, None, None, None) == 0
     assert lib.pt_sweep_record(None, 10, None, 0) == -1
+
+
+@pytest.mark.parametrize("L,missing", [(1, 0.0), (2, 0.0), (3, 0.05)])
+def test_lao_matches_oracle(L, missing):
+    """Planted instances and loop moves of the library equal the oracle's:
+    cycle counts, loops, planted bits, couplings, ground-state energies."""
+    import oracle.lao as P
+    hs = _hs()
+    live = workloads.missing_mask(L, missing, 13, L) if missing else None
+    cyc = P.cycles(L, live)
+    for n in (4, 6):
+        assert hs.lao_cycle_count(L, n, live) == len(cyc[n])
+    M = {1: 5, 2: 14, 3: 40}[L]
+    for chain in range(3):
+        got = hs.lao_init(L, M, chain, 21, live)
+        want = P.init(L, M, chain, 21, live=live, cyc=cyc)
+        assert [tuple(r) for r in got["loops"].tolist()] == [tuple(x) for x in want["loops"]]
+        assert np.array_equal(got["bits"], want["bits"])
+        assert np.array_equal(got["J"], want["J"]) and got["e_gs"] == want["e_gs"]
+        for step in range(4):
+            g = hs.lao_move(L, got, chain, 21, step, 1, live)
+            w = P.move(L, want, chain, 21, step, 1, live=live, cyc=cyc)
+            assert g[0] == w[0] and g[2] == w[2]
+            assert g[0] < 0 or g[1] == tuple(w[1])
+            assert np.array_equal(g[3], w[3]) and g[4] == w[4]
+
+
+def test_lao_rejects_bad_arguments():
+    hs = _hs()
+    with pytest.raises(RuntimeError):
+        hs.lao_init(0, 5, 0, 0)
+    with pytest.raises(RuntimeError):
+        hs.lao_init(2, 0, 0, 0)
+    with pytest.raises(RuntimeError):
+        hs.lao_cycle_count(2, 5)
+    inst = hs.lao_init(2, 6, 0, 0)
+    bad = dict(inst, loops=inst["loops"].copy())
+    bad["loops"][2, 1] = 10 ** 6
+    with pytest.raises(RuntimeError):
+        hs.lao_move(2, bad, 0, 0, 1, 0)
+
+
+def test_lao_moves_keep_the_cap_and_match_oracle_on_dense_c4():
+    """Dense loops (120 on C4): removing a loop can push a shared coupler
+    past |J| = 7, so some proposals are void; every candidate stays within
+    the cap and library and oracle agree move by move."""
+    import oracle.lao as P
+    hs = _hs()
+    cyc = P.cycles(4)
+    g = hs.lao_init(4, 120, 2, 8)
+    o = P.init(4, 120, 2, 8, cyc=cyc)
+    voids = 0
+    for step in range(60):
+        a = hs.lao_move(4, g, 2, 8, step, 0)
+        b = P.move(4, o, 2, 8, step, 0, cyc=cyc)
+        assert a[0] == b[0] and np.array_equal(a[3], b[3]) and a[4] == b[4]
+        assert int(np.abs(a[3].astype(int)).max()) <= 7
+        if a[0] < 0:
+            voids += 1
+            assert np.array_equal(a[3], g["J"])
+            continue
+        g = dict(g, loops=g["loops"].copy(), J=a[3], e_gs=a[4])
+        g["loops"][a[0]] = a[1]
+        o = dict(o, loops=list(o["loops"]), J=b[3], e_gs=b[4])
+        o["loops"][b[0]] = b[1]
+        J, e = P.couplings(4, o["loops"], cyc, o["bits"])
+        assert np.array_equal(J, a[3]) and e == a[4]
+    assert voids > 0
