@@ -255,6 +255,38 @@ int lao_move(int L, const uint8_t *live, int n_loops, uint32_t chain, uint32_t s
              uint32_t proposal, const hs_loop *loops, const uint8_t *planted, int32_t *slot, hs_loop *new_loop,
              uint32_t *w_accept, int8_t *J_new, int64_t *e_gs_new);
 
+/* Ground / first-excited overlaps from PT snapshots (Sec. III.B, Fig. 3).
+ *
+ * pt_capture enqueues on h's stream, for every instance n and live lane l
+ * whose current energy is at most e_cap[n] (device int32 [n_inst]): one slot
+ * from the atomic *count (device uint32, the caller clears it), and, when the
+ * slot is below capacity, configs[slot n_words + w] = the lane's spins
+ * bit-packed (bit b of word w = site 64 w + b, 0 for missing sites) and
+ * meta[slot 4 + 0..3] = (n, l, energy, completed sweeps).  Slots past
+ * capacity are counted but not written.  n_words >= ceil(8 L^2 / 64) for the
+ * largest lattice of the batch, else HS_EINVAL.  Asynchronous.
+ *
+ * overlap_analyze takes n captured configurations of ONE instance (device
+ * configs [n][n_words], host energies [n]), the live-site mask (device
+ * [n_words], bit = site live) and its popcount n_live, and a device scratch of
+ * n x n int32.  It computes all pairwise Hamming distances h on the device,
+ * then on the host: the ground level e0 = the lowest energy present, the
+ * first excited level e1 = the next one; the distinct configurations of each
+ * level up to the global flip (h = 0 or n_live to an earlier kept one);
+ * overlaps q = |1 - 2 h / n_live|; med_gg = median q over pairs of distinct
+ * ground states (1 with one ground state); med_ge = median q over (ground,
+ * excited) pairs; ratio = med_ge / med_gg.  has_excited = 0 (and n_ex,
+ * med_ge, ratio = 0) with a single level.  Synchronises the stream.
+ * HS_EINVAL for bad arguments or n > 46340. */
+typedef struct hs_overlap {
+    int32_t e0, e1, n_gs, n_ex, has_excited, pad_;
+    double med_gg, med_ge, ratio;
+} hs_overlap;
+int pt_capture(hs_pt *h, const int32_t *e_cap, uint64_t *configs, int32_t *meta, uint32_t *count,
+               int64_t capacity, int n_words);
+int overlap_analyze(const uint64_t *configs, const int32_t *energy, int n, int n_words, const uint64_t *mask,
+                    int n_live, int32_t *scratch, void *stream, hs_overlap *out);
+
 /* Hardness of candidate instances: n_restarts independent PT runs per
  * candidate (restart rho keyed by (word 0 of Philox((instance_id, seed),
  * (rho, 0, 0, 5)), seed)), each until replica agreement or s_max sweeps

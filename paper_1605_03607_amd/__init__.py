@@ -93,6 +93,9 @@ def lib():
         L.pt_sweep_record.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]
         L.walk_autocorr.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
+        L.pt_capture.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int]
+        L.overlap_analyze.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
+                                      C.c_void_p, C.POINTER(hs_overlap)]
         L.lao_cycle_count.argtypes = [C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_int64)]
         L.lao_init.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.POINTER(C.c_int64)]
@@ -156,12 +159,18 @@ def exported_symbols():
             "pt_autotune", "instance_mutate", "hs_rao_accept", "hardness_workspace_bytes",
             "hardness_eval", "gnn_param_count", "gnn_workspace_bytes", "gnn_prepare", "gnn_forward",
             "gnn_train_step", "pt_sweep_record", "walk_autocorr", "walk_tau", "lao_cycle_count", "lao_init",
-            "lao_move"]
+            "lao_move", "pt_capture", "overlap_analyze"]
 
 
 def _check(rc):
     if rc != 0:
         raise HardspinError(rc, lib().hs_last_error().decode())
+
+
+class hs_overlap(C.Structure):
+    _fields_ = [("e0", C.c_int32), ("e1", C.c_int32), ("n_gs", C.c_int32), ("n_ex", C.c_int32),
+                ("has_excited", C.c_int32), ("pad_", C.c_int32), ("med_gg", C.c_double),
+                ("med_ge", C.c_double), ("ratio", C.c_double)]
 
 
 class _HostInstances:
@@ -238,6 +247,20 @@ class PTBatch:
                 walk.shape[2] != 64 or not walk.is_contiguous() or not walk.is_cuda:
             raise ValueError("walk must be a contiguous CUDA uint8 tensor [n_inst, capacity, 64]")
         _check(lib().pt_sweep_record(self.h, int(n_sweeps), C.c_void_p(walk.data_ptr()), int(walk.shape[1])))
+
+    def capture(self, e_cap, configs, meta, count):
+        """pt_capture into device tensors: configs int64 [capacity, n_words],
+        meta int32 [capacity, 4], count int32 [1] (cleared by the caller);
+        e_cap: energy cap per instance (sequence of ints)."""
+        torch = _torch()
+        cap = torch.as_tensor(np.ascontiguousarray(e_cap, np.int32)).to(self.spins.device)
+        self._cap_keep = cap
+        for t, dt in ((configs, torch.int64), (meta, torch.int32), (count, torch.int32)):
+            if t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("capture buffers: contiguous CUDA int64 configs, int32 meta and count")
+        _check(lib().pt_capture(self.h, C.c_void_p(cap.data_ptr()), C.c_void_p(configs.data_ptr()),
+                                C.c_void_p(meta.data_ptr()), C.c_void_p(count.data_ptr()), int(configs.shape[0]),
+                                int(configs.shape[1])))
 
     def graph(self, n_sweeps):
         """A captured HIP graph whose replay runs n_sweeps more sweeps."""
@@ -386,6 +409,35 @@ def hardness_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed, blo
                     n_censored=det[i].n_censored, sweeps_total=det[i].sweeps_total)
                for i in range(len(cands))]
     return ln, details
+
+
+# ---------------------------------------------------------------------------
+# Ground / first-excited overlaps (hardspin.h).
+def overlap_analyze(configs, energies, live_bits_words, n_live, stream=None):
+    """configs: host uint64 [n, n_words] of one instance; energies: [n];
+    live_bits_words: host uint64 [n_words] mask of live sites."""
+    torch = _torch()
+    cfg = torch.from_numpy(np.ascontiguousarray(configs, np.uint64).view(np.int64)).cuda()
+    mask = torch.from_numpy(np.ascontiguousarray(live_bits_words, np.uint64).view(np.int64)).cuda()
+    e = np.ascontiguousarray(energies, np.int32)
+    n, w = cfg.shape
+    scratch = torch.zeros(max(1, n * n), dtype=torch.int32, device=cfg.device)
+    out = hs_overlap()
+    _check(lib().overlap_analyze(C.c_void_p(cfg.data_ptr()), e.ctypes.data, int(n), int(w),
+                                 C.c_void_p(mask.data_ptr()), int(n_live), C.c_void_p(scratch.data_ptr()),
+                                 _stream_ptr(stream), C.byref(out)))
+    return dict(e0=out.e0, e1=out.e1 if out.has_excited else None, n_gs=out.n_gs, n_ex=out.n_ex,
+                med_gg=out.med_gg, med_ge=out.med_ge if out.has_excited else None,
+                ratio=out.ratio if out.has_excited else None)
+
+
+def pack_sites(bits):
+    """uint8 [N] site bits -> uint64 words, bit b of word w = site 64 w + b."""
+    b = np.asarray(bits, np.uint8)
+    words = np.zeros((len(b) + 63) // 64, np.uint64)
+    for i in np.nonzero(b)[0]:
+        words[i // 64] |= np.uint64(1) << np.uint64(i % 64)
+    return words
 
 
 # ---------------------------------------------------------------------------

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhardspin.so")
 PROBE_LIB = os.path.join(HERE, "libhsprobe.so")
-SOURCES = ["hs_host.cpp", "hs_hardness.cpp", "hs_lao.cpp", "hs_pt.hip", "hs_gnn.hip", "hs_walk.hip"]
+SOURCES = ["hs_host.cpp", "hs_hardness.cpp", "hs_lao.cpp", "hs_pt.hip", "hs_gnn.hip", "hs_walk.hip", "hs_overlap.hip"]
 ARCH = os.environ.get("HARDSPIN_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for every HIP translation unit.

@@ -938,6 +938,35 @@ __global__ void __launch_bounds__(64) k_energy(const InstDev *inst, const uint32
     if (lane < d.nlanes && ev != energy[n * 64 + lane]) atomicAdd(mismatch, 1);
 }
 
+// Configurations of the live lanes whose energy is at most e_cap[n]
+// (pt_capture), one wavefront per instance and thread per lane: each
+// selected lane takes an output slot from an atomic counter and writes its
+// spins bit-packed (bit b of word w = site 64 w + b) and (n, lane, energy, t).
+__global__ void __launch_bounds__(64) k_capture(const InstDev *inst, const uint64_t *spins, const int32_t *energy,
+                                                const int64_t *tsweep, const int32_t *e_cap, uint64_t *configs,
+                                                int32_t *meta, uint32_t *count, int64_t capacity, int n_words)
+{
+    const int n = blockIdx.x, lane = threadIdx.x;
+    const InstDev d = inst[n];
+    const int e = energy[n * 64 + lane];
+    if (lane >= d.nlanes || e > e_cap[n]) return;
+    const uint32_t at = atomicAdd(count, 1u);
+    if (int64_t(at) >= capacity) return;
+    const uint64_t *sp = spins + d.spin_off;
+    for (int w = 0; w < n_words; ++w) {
+        uint64_t word = 0;
+        for (int b = 0; b < 64; ++b) {
+            const int i = 64 * w + b;
+            if (i < d.n_sites) word |= ((sp[i] >> lane) & 1ull) << b;
+        }
+        configs[int64_t(at) * n_words + w] = word;
+    }
+    meta[int64_t(at) * 4 + 0] = n;
+    meta[int64_t(at) * 4 + 1] = lane;
+    meta[int64_t(at) * 4 + 2] = e;
+    meta[int64_t(at) * 4 + 3] = int32_t(tsweep[n]);
+}
+
 // One extra exchange pass per instance (pt_swap), one wavefront each.
 __global__ void __launch_bounds__(64) k_swap_extra(const InstDev *inst, const TableDev *tabs,
                                                    const uint32_t *ws32, uint8_t *perm_g,
@@ -1533,6 +1562,21 @@ int pt_measure(hs_pt *h, int32_t *recomputed, int32_t *n_mismatch)
     HIP_TRY(hipStreamSynchronize(h->stream));
     if (n_mismatch) *n_mismatch = host_mm;
     if (host_mm != 0) return fail(HS_EMISMATCH, "pt_measure: incremental and recomputed energies differ");
+    return HS_OK;
+}
+
+int pt_capture(hs_pt *h, const int32_t *e_cap, uint64_t *configs, int32_t *meta, uint32_t *count, int64_t capacity,
+               int n_words)
+{
+    if (h == nullptr || e_cap == nullptr || configs == nullptr || meta == nullptr || count == nullptr ||
+        capacity < 0 || n_words < (8 * h->ncell_max + 63) / 64)
+        return fail(HS_EINVAL, "pt_capture: bad arguments");
+    if (h->n_inst == 0) return HS_OK;
+    char *ws = reinterpret_cast<char *>(h->buf.workspace);
+    hipLaunchKernelGGL(dev::k_capture, dim3(h->n_inst), dim3(64), 0, h->stream,
+                       reinterpret_cast<const InstDev *>(ws + h->off_inst * 4), h->buf.spins, h->buf.energy, h->buf.t,
+                       e_cap, configs, meta, count, capacity, n_words);
+    HIP_TRY(hipGetLastError());
     return HS_OK;
 }
 
