@@ -79,7 +79,8 @@ def parse():
     p.add_argument("--copy-mib", type=int, default=0,
                    help="after the timed steps, run one plain device copy of this many MiB "
                         "(reference kernel for scaling HBM byte counters)")
-    p.add_argument("--workload", choices=["c8", "uneven", "search", "search-reverse", "surrogate", "tau", "lao"],
+    p.add_argument("--workload", choices=["c8", "uneven", "search", "search-reverse", "surrogate", "tau", "lao",
+                                          "overlap"],
                    default="c8",
                    help="c8: the 256 x C8 batch (default); uneven: 1024 instances C4..C12, "
                         "autotuned shape, HIP-graph replay, live attempts/s; search: bounded "
@@ -377,6 +378,84 @@ def lao(args):
     print(json.dumps(out), flush=True)
 
 
+def overlap(args):
+    """Fig. 3's two hardness measures on the same runs: 256 C8 instances
+    (J = +-1, K32 R2, EMCS = 10 sweeps + one exchange pass) run --tau-emcs
+    EMCS with the temperature walk recorded (tau), then 300 more EMCS with
+    a snapshot after each, capturing every lane within 4 of the instance's
+    lowest energy so far; per instance the ground / first-excited median
+    overlap ratio, and the rank correlation of ratio and tau over the
+    instances whose tau window converged."""
+    import torch
+
+    import paper_1605_03607_amd as hs
+    n_inst, K, R, si, L = 256, 32, 2, 10, 8
+    T = args.tau_emcs
+    max_lag = min(65535, max(1, T // 4))
+    beta = workloads.geometric_betas(0.1, 5.0, K)
+    insts = [dict(L=L, J=workloads.couplings(L, "pm1", 3033, n), live=None, K=K, R=R, beta=beta, instance_id=n)
+             for n in range(n_inst)]
+    b = hs.PTBatch(insts, 3033, swap_interval=si)
+    walk = torch.zeros((n_inst, T, 64), dtype=torch.uint8, device="cuda")
+    t0 = time.perf_counter()
+    b.sweep_record(T * si, walk)
+    acf, hot = hs.walk_autocorr(walk, T, K, R, max_lag)
+    del walk
+    taus = [hs.walk_tau(acf[n], T) for n in range(n_inst)]
+    e_min = [int(b.state(n)["emin"].min()) for n in range(n_inst)]
+    n_words, capacity, n_snap = (8 * L * L + 63) // 64, 1 << 22, 300
+    configs = torch.zeros((capacity, n_words), dtype=torch.int64, device="cuda")
+    meta = torch.zeros((capacity, 4), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    caps = [e + 4 for e in e_min]
+    for _ in range(n_snap):
+        b.sweep(si)
+        b.capture(caps, configs, meta, count)
+    torch.cuda.synchronize()
+    t_pt = time.perf_counter() - t0
+    n_cap = min(int(count.item()), capacity)
+    cfg_h = configs[:n_cap].cpu().numpy().view(np.uint64)
+    meta_h = meta[:n_cap].cpu().numpy()
+    mask = np.full(n_words, np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64)
+    t1 = time.perf_counter()
+    ratios = []
+    for n in range(n_inst):
+        rows = np.nonzero(meta_h[:, 0] == n)[0]
+        if len(rows) == 0:
+            ratios.append(None)
+            continue
+        # repeated snapshots of one configuration change nothing in the analysis
+        key = np.concatenate([meta_h[rows, 2:3].astype(np.uint64), cfg_h[rows]], axis=1)
+        _, first = np.unique(key, axis=0, return_index=True)
+        sel = rows[np.sort(first)][:2000]
+        s = hs.overlap_analyze(cfg_h[sel], meta_h[sel, 2], mask, 8 * L * L)
+        ratios.append(s["ratio"])
+    t_ov = time.perf_counter() - t1
+    pairs = [(taus[n][0] * si, ratios[n]) for n in range(n_inst) if taus[n][2] and ratios[n] is not None]
+    rho = None
+    if len(pairs) >= 3:
+        a = np.argsort(np.argsort([p[0] for p in pairs])).astype(float)
+        c = np.argsort(np.argsort([p[1] for p in pairs])).astype(float)
+        rho = float(np.corrcoef(a, c)[0, 1])
+    valid = [r for r in ratios if r is not None]
+    out = {
+        "metric": "ground / first-excited overlap ratio and mixing time (Fig. 3)",
+        "value": float(np.median(valid)) if valid else None,
+        "unit": "median over instances of (median GS-ES overlap / median GS-GS overlap)",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": (t_pt + t_ov) * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32 (PT) / int64 (sums)", "data": "synthetic",
+        "config": {"workload": f"overlap + tau, {n_inst} C8 instances J=+-1, K{K} R{R}, EMCS = {si} sweeps + 1 exchange, "
+                               f"{T} EMCS walk then {n_snap} snapshot EMCS, cap E_min + 4"},
+        "captured": int(count.item()), "stored": n_cap, "instances_with_excited_level": len(valid),
+        "tau_converged": int(sum(t[2] for t in taus)),
+        "spearman_tau_vs_ratio": rho, "pairs": len(pairs),
+        "pt_seconds": t_pt, "overlap_seconds": t_ov,
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def surrogate(args):
     """Surrogate step times on C8 graphs: a training step (forward, backward,
     Adam) on the 16-graph batch and the forward pass that screens 1024
@@ -427,6 +506,9 @@ def main():
         sys.exit(2)
     if args.workload == "uneven":
         uneven(args)
+        return
+    if args.workload == "overlap":
+        overlap(args)
         return
     if args.workload == "lao":
         lao(args)
