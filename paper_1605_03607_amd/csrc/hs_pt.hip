@@ -502,6 +502,9 @@ __device__ __forceinline__ int site_m4(uint32_t own, uint32_t oth, uint32_t xv, 
 // slot energies, accumulated in LDS with atomics.  Every wavefront then keeps
 // its own copy of the running minima (identical in all wavefronts) and, when
 // an exchange pass is due, the two exchange steps add two barriers.
+// kRecord: also write the temperature walk (pt_sweep_record); a separate
+// instantiation keeps the plain sweep free of the recording code.
+template <bool kRecord>
 __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
 {
     extern __shared__ __align__(16) char lds[];
@@ -643,7 +646,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             if (nt > 1) pre1 = metro_call(ml, m, task[((wave * 2) * iters + 1) * 8], RK);
         };
         predraw(metro_uniform(uint32_t(t), kUseMetroHi, key0, key1));
-        int64_t n_ex = 0;  // exchange passes made in this launch
+        int64_t n_ex = 0;  // exchange passes made in this launch (recording only)
 
         for (int64_t sw = 0; sw < a.n_sweeps && !stopped; ++sw) {
             const uint32_t tt = uint32_t(t);
@@ -805,10 +808,12 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                 __syncthreads();
                 if (wave < nwalk) predraw(mu_next);
                 col = live ? perm[lane] : lane;
-                // temperature walk: configuration col now sits at temperature kslot
-                if (a.walk != nullptr && wave == nwaves - 1 && n_ex < a.walk_cap && live)
-                    a.walk[(int64_t(n) * a.walk_cap + n_ex) * 64 + col] = uint8_t(kslot);
-                ++n_ex;
+                if constexpr (kRecord) {
+                    // temperature walk: configuration col now sits at temperature kslot
+                    if (wave == nwaves - 1 && n_ex < a.walk_cap && live)
+                        a.walk[(int64_t(n) * a.walk_cap + n_ex) * 64 + col] = uint8_t(kslot);
+                    ++n_ex;
+                }
             } else {
                 predraw(mu_next);
             }
@@ -1337,9 +1342,12 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
         delete h;
         return hip_fail(e, "pt_init: launch");
     }
-    const void *kfn = reinterpret_cast<const void *>(&dev::k_pt_sweep);
+    const void *kfn = reinterpret_cast<const void *>(&dev::k_pt_sweep<false>);
+    const void *kfn_rec = reinterpret_cast<const void *>(&dev::k_pt_sweep<true>);
     if (h->lds_bytes > 64 * 1024) {
         e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(h->lds_bytes));
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(kfn_rec, hipFuncAttributeMaxDynamicSharedMemorySize, int(h->lds_bytes));
         if (e != hipSuccess) {
             delete h;
             return hip_fail(e, "pt_init: LDS size");
@@ -1391,7 +1399,10 @@ int sweep_launch(hs_pt *h, int64_t n_sweeps, hipStream_t stream, uint8_t *walk =
     a.walk = walk;
     a.walk_cap = walk_cap;
     hipLaunchKernelGGL(dev::k_reset_queue, dim3(1), dim3(1), 0, stream, a.queue);
-    hipLaunchKernelGGL(dev::k_pt_sweep, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, stream, a);
+    if (walk != nullptr)
+        hipLaunchKernelGGL(dev::k_pt_sweep<true>, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, stream, a);
+    else
+        hipLaunchKernelGGL(dev::k_pt_sweep<false>, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "pt_sweep: launch");
     return HS_OK;
