@@ -87,6 +87,8 @@ def parse():
                         "plain / surrogate-screened / random-screened instance search")
     p.add_argument("--search-steps", type=int, default=20)
     p.add_argument("--search-chains", type=int, default=64)
+    p.add_argument("--search-groups", type=int, default=1,
+                   help="chain groups stepping concurrently on their own streams (search workloads)")
     p.add_argument("--tau-emcs", type=int, default=20000, help="EMCS of the --workload tau run")
     p.add_argument("--probe", action="store_true",
                    help="also measure instruction issue rates (libhsprobe.so)")
@@ -195,6 +197,13 @@ def uneven(args):
     print(json.dumps(out), flush=True)
 
 
+def _search_progress(name, args):
+    def report(group, step):
+        print(f"# {name}: group {group + 1}/{args.search_groups} step {step}/{args.search_steps}",
+              file=sys.stderr, flush=True)
+    return report
+
+
 def search(args):
     """Hard instances per hour of the instance search (Algorithm 1) on C8:
     plain chains, surrogate-screened chains and the random-screen ablation,
@@ -210,12 +219,11 @@ def search(args):
         cfg = S.SearchConfig(mode=mode, chains=args.search_chains)
         params = workloads.gnn_params(hs.lib().gnn_param_count(), hs.gnn_fan_ins())
         t0 = time.perf_counter()
-        run = S.Search(cfg, seeds, surrogate_params=params if mode == "surrogate" else None)
+        run = S.GroupedSearch(cfg, seeds, groups=args.search_groups,
+                              surrogate_params=params if mode == "surrogate" else None)
         t_init = time.perf_counter() - t0
         t0 = time.perf_counter()
-        for k in range(args.search_steps):
-            run.run_step(bars=tuple(bars.values()))
-            print(f"# {mode}: step {k + 1}/{args.search_steps}", file=sys.stderr, flush=True)
+        run.run(args.search_steps, bars=tuple(bars.values()), progress=_search_progress(mode, args))
         wall = time.perf_counter() - t0
         hours = wall / 3600.0
         hard = {name: len(run.hard.get(b, set())) for name, b in bars.items()}
@@ -240,7 +248,7 @@ def search(args):
         "dtype": "int32 (PT) / bf16-fp32 (surrogate)", "data": "synthetic",
         "config": {"workload": f"instance search, {args.search_chains} C8 chains, +-1 seeds, "
                                "mutations in +-1..+-7, 32 restarts K32 R2, T_s 0.5",
-                   "bounded_steps": args.search_steps},
+                   "bounded_steps": args.search_steps, "chain_groups": args.search_groups},
         "surrogate_over_plain": (rate("surrogate") / rate("plain")) if rate("plain") > 0 else None,
         "arms": arms,
     }
@@ -258,12 +266,10 @@ def search_reverse(args):
     seeds = workloads.search_seeds(args.search_chains)
     bars = {"ln3": math.log(3.0), "ln10": math.log(10.0)}
     cfg = S.SearchConfig(mode="plain", chains=args.search_chains, direction=-1, alphabet=S.ALPHABET_PM1)
-    run = S.Search(cfg, seeds)
+    run = S.GroupedSearch(cfg, seeds, groups=args.search_groups)
     h0 = run.h0
     t0 = time.perf_counter()
-    for k in range(args.search_steps):
-        run.run_step(bars=tuple(bars.values()))
-        print(f"# reverse: step {k + 1}/{args.search_steps}", file=sys.stderr, flush=True)
+    run.run(args.search_steps, bars=tuple(bars.values()), progress=_search_progress("reverse", args))
     wall = time.perf_counter() - t0
     easy = {name: len(run.hard.get(b, set())) for name, b in bars.items()}
     med = float(np.median(run.ln))
@@ -277,7 +283,7 @@ def search_reverse(args):
         "dtype": "int32 (PT)", "data": "synthetic",
         "config": {"workload": f"reversed instance search, {args.search_chains} C8 chains, +-1 seeds, "
                                "sign-flip mutations (J stays +-1), 32 restarts K32 R2, T_s 0.5",
-                   "bounded_steps": args.search_steps},
+                   "bounded_steps": args.search_steps, "chain_groups": args.search_groups},
         "easy_instances": easy, "h0_ln_tts": h0, "final_median_ln_tts": med,
         "median_drop_ln": h0 - med, "accepted": run.accepted, "pt_sweeps": int(run.pt_sweeps),
     }

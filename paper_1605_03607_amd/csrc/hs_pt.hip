@@ -1256,12 +1256,12 @@ int hip_fail(hipError_t e, const char *what)
 
 int device_cus()
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
+    static const int cus = [] {  // thread-safe one-time initialisation
+        int dev = 0, n = 1;
         if (hipGetDevice(&dev) != hipSuccess) return 1;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
-    }
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+        return n;
+    }();
     return cus;
 }
 

@@ -25,9 +25,20 @@ the lowest predicted ln TTS, the better of the PT-scored candidates is the
 one with the lower ln TTS, and the counted states are the easy ones,
 ln TTS <= H0 - ln(bar).  Every acceptance decision is logged in `decisions`
 as (step, chain, ln_cur, ln_new, w, accepted).
+
+GroupedSearch runs the chains of one search as G groups, each group stepping
+in its own host thread on its own stream.  One PT launch lasts as long as its
+slowest restart, and the runs that stop early leave most of the chip idle
+during that tail; launches of the other groups fill it.  The groups share the
+surrogate and its replay buffer (under a lock).  Chains keep their global
+indices, so every random draw (PT streams, mutations, the random screen) is
+the one the single-group search makes: plain and random searches take the
+same decisions under any grouping; the surrogate arm's training order, and
+with it its screen, depends on the order in which groups finish.
 """
 import hashlib
 import math
+import threading
 import time
 
 import numpy as np
@@ -65,24 +76,61 @@ def _key(J):
     return hashlib.sha1(np.ascontiguousarray(J, np.int8).tobytes()).hexdigest()
 
 
+class _Pool:
+    """What the chain groups of one search share: the surrogate, the replay
+    buffer of PT-scored (J, ln TTS) pairs and the training draws."""
+
+    def __init__(self, cfg, surrogate_params):
+        self.sur = Surrogate(surrogate_params) if cfg.mode == "surrogate" else None
+        self.pairs_J, self.pairs_y = [], []
+        self.rng = np.random.default_rng(cfg.seed + 77)
+        self.lock = threading.Lock()
+        self.gnn_seconds = 0.0
+        self.replay = cfg.replay
+
+    def add(self, cands, ln):
+        with self.lock:
+            for cd, y in zip(cands, ln):
+                if math.isfinite(y):
+                    self.pairs_J.append(np.array(cd["J"], np.int8))
+                    self.pairs_y.append(float(y))
+            if len(self.pairs_J) > self.replay:
+                self.pairs_J = self.pairs_J[-self.replay:]
+                self.pairs_y = self.pairs_y[-self.replay:]
+
+
 class Search:
-    def __init__(self, cfg, seeds, surrogate_params=None):
+    """One search over `seeds`.  chain_ids (default 0..n-1) are the chains'
+    global indices, which key every random draw; a group of a GroupedSearch
+    passes its slice of them with the shared pool and the seeds' scores."""
+
+    def __init__(self, cfg, seeds, surrogate_params=None, chain_ids=None, pool=None, ln=None, h0=None):
         self.cfg = cfg
         self.J = [np.array(s, np.int8) for s in seeds]
+        self.ids = list(range(len(self.J))) if chain_ids is None else [int(i) for i in chain_ids]
+        if len(self.ids) != len(self.J):
+            raise ValueError("one chain id per seed")
         self.step = 0
         self.pt_seconds = 0.0
-        self.gnn_seconds = 0.0
         self.pt_sweeps = 0
-        self.pairs_J, self.pairs_y = [], []
-        self.sur = None
-        if cfg.mode == "surrogate":
-            self.sur = Surrogate(surrogate_params)
-        self.rng = np.random.default_rng(cfg.seed + 77)
-        self.ln = self._score([dict(L=cfg.L, J=J, live=None, instance_id=c) for c, J in enumerate(self.J)])
-        self.h0 = float(np.median(self.ln))
+        self.pool = _Pool(cfg, surrogate_params) if pool is None else pool
+        # training steps per step in proportion to the chains this search holds
+        self.train_steps = max(1, round(cfg.train_steps * len(self.J) / cfg.chains))
+        if ln is None:
+            ln = self._score([dict(L=cfg.L, J=J, live=None, instance_id=i) for i, J in zip(self.ids, self.J)])
+        self.ln = np.array(ln, np.float64)
+        self.h0 = float(np.median(self.ln)) if h0 is None else float(h0)
         self.accepted = 0
         self.hard = {}
         self.decisions = []
+
+    @property
+    def gnn_seconds(self):
+        return self.pool.gnn_seconds
+
+    @property
+    def sur(self):
+        return self.pool.sur
 
     def _score(self, cands):
         c = self.cfg
@@ -90,20 +138,14 @@ class Search:
         ln, det = hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
         self.pt_seconds += time.perf_counter() - t0
         self.pt_sweeps += sum(d["sweeps_total"] for d in det)
-        for cd, y in zip(cands, ln):
-            if math.isfinite(y):
-                self.pairs_J.append(np.array(cd["J"], np.int8))
-                self.pairs_y.append(float(y))
-        if len(self.pairs_J) > c.replay:
-            self.pairs_J = self.pairs_J[-c.replay:]
-            self.pairs_y = self.pairs_y[-c.replay:]
+        self.pool.add(cands, ln)
         return ln
 
     def _proposals(self, chain):
         c = self.cfg
         out = []
         for p in range(c.proposals):
-            e, old, new, w = instance_mutate(dict(L=c.L, J=self.J[chain], live=None), c.alphabet, chain,
+            e, old, new, w = instance_mutate(dict(L=c.L, J=self.J[chain], live=None), c.alphabet, self.ids[chain],
                                              c.seed, self.step, p)
             J2 = self.J[chain].copy()
             J2[e] = new
@@ -114,40 +156,53 @@ class Search:
         """Surrogate predictions for every (chain, proposal)."""
         c = self.cfg
         flat = [J for pr in props for (J, _, _) in pr]
-        t0 = time.perf_counter()
+        pool = self.pool
         pred = []
-        for a in range(0, len(flat), c.screen_chunk):
-            pred.append(self.sur.forward([(c.L, None, J) for J in flat[a:a + c.screen_chunk]]))
-        self.gnn_seconds += time.perf_counter() - t0
+        with pool.lock:  # every call ends with a host copy: nothing is left in flight
+            t0 = time.perf_counter()
+            for a in range(0, len(flat), c.screen_chunk):
+                pred.append(pool.sur.forward([(c.L, None, J) for J in flat[a:a + c.screen_chunk]]))
+            pool.gnn_seconds += time.perf_counter() - t0
         return np.concatenate(pred).reshape(len(props), c.proposals)
 
     def _train(self):
         c = self.cfg
-        if self.sur is None or len(self.pairs_J) < c.train_batch:
+        pool = self.pool
+        if pool.sur is None:
             return
-        t0 = time.perf_counter()
-        for _ in range(c.train_steps):
-            idx = self.rng.choice(len(self.pairs_J), size=c.train_batch, replace=False)
-            self.sur.train_step(np.array([self.pairs_y[i] for i in idx]),
-                                graphs=[(c.L, None, self.pairs_J[i]) for i in idx], lr=c.lr)
-        self.gnn_seconds += time.perf_counter() - t0
+        with pool.lock:
+            if len(pool.pairs_J) < c.train_batch:
+                return
+            t0 = time.perf_counter()
+            for _ in range(self.train_steps):
+                idx = pool.rng.choice(len(pool.pairs_J), size=c.train_batch, replace=False)
+                pool.sur.train_step(np.array([pool.pairs_y[i] for i in idx]),
+                                    graphs=[(c.L, None, pool.pairs_J[i]) for i in idx], lr=c.lr)
+            pool.gnn_seconds += time.perf_counter() - t0
+
+    def _random_screen(self, chain):
+        """The ablation's `top` proposals of one chain at this step, drawn from
+        a generator keyed by (seed, step, global chain index)."""
+        c = self.cfg
+        g = np.random.default_rng([c.seed, 0x5C4EE7, self.step, self.ids[chain]])
+        return sorted(g.choice(c.proposals, size=c.top, replace=False).tolist())
 
     def run_step(self, bars=(math.log(3.0), math.log(10.0), math.log(30.0))):
         c = self.cfg
-        props = [self._proposals(ch) for ch in range(c.chains)]
+        n = len(self.J)
+        props = [self._proposals(ch) for ch in range(n)]
         if c.mode == "plain":
-            chosen = [[0] for _ in range(c.chains)]
+            chosen = [[0] for _ in range(n)]
         elif c.mode == "surrogate":
             pred = self._rank(props) * c.direction
-            chosen = [sorted(np.argsort(-pred[ch], kind="stable")[:c.top].tolist()) for ch in range(c.chains)]
+            chosen = [sorted(np.argsort(-pred[ch], kind="stable")[:c.top].tolist()) for ch in range(n)]
         else:
-            chosen = [sorted(self.rng.choice(c.proposals, size=c.top, replace=False).tolist())
-                      for _ in range(c.chains)]
+            chosen = [self._random_screen(ch) for ch in range(n)]
         cands, owner = [], []
-        for ch in range(c.chains):
+        for ch in range(n):
             for p in chosen[ch]:
                 J2, _, _ = props[ch][p]
-                cands.append(dict(L=c.L, J=J2, live=None, instance_id=ch))
+                cands.append(dict(L=c.L, J=J2, live=None, instance_id=self.ids[ch]))
                 owner.append((ch, p))
         ln = self._score(cands)
         best = {}
@@ -155,11 +210,11 @@ class Search:
         for (ch, p), y in zip(owner, ln):
             if ch not in best or d * y > d * best[ch][1]:  # ties keep the lower proposal index
                 best[ch] = (p, y)
-        for ch in range(c.chains):
+        for ch in range(n):
             p, y = best[ch]
             J2, w, _ = props[ch][p]
             ok = rao_accept(d * self.ln[ch], d * y, c.t_s, w)
-            self.decisions.append((self.step, ch, float(self.ln[ch]), float(y), int(w), bool(ok)))
+            self.decisions.append((self.step, self.ids[ch], float(self.ln[ch]), float(y), int(w), bool(ok)))
             if ok:
                 self.J[ch] = J2
                 self.ln[ch] = y
@@ -170,6 +225,100 @@ class Search:
         self._train()
         self.step += 1
 
+
+def _group_stream():
+    """A new stream (default priority) and the context that makes it the
+    calling thread's current one."""
+    import torch
+    s = torch.cuda.Stream()
+    return s, torch.cuda.stream(s)
+
+
+class GroupedSearch:
+    """The chains of one search in `groups` contiguous groups that step
+    concurrently, each in a host thread with a stream of its own (default
+    priority).  The seeds are scored in one call, so H0 is the median over
+    all chains as in Search.  The attributes mirror Search's, merged over the
+    groups; pt_seconds sums the groups' (overlapping) PT calls."""
+
+    def __init__(self, cfg, seeds, groups=4, surrogate_params=None):
+        n = len(seeds)
+        if not 1 <= groups <= n:
+            raise ValueError("need 1 <= groups <= chains")
+        head = Search(cfg, seeds, surrogate_params)
+        self.cfg = cfg
+        self.pool = head.pool
+        self.h0 = head.h0
+        self.init_pt_seconds = head.pt_seconds
+        self.init_pt_sweeps = head.pt_sweeps
+        cuts = [round(g * n / groups) for g in range(groups + 1)]
+        self.groups = [Search(cfg, seeds[a:b], chain_ids=range(a, b), pool=self.pool, ln=head.ln[a:b], h0=head.h0)
+                       for a, b in zip(cuts[:-1], cuts[1:])]
+
+    def run(self, steps, bars=(math.log(3.0), math.log(10.0), math.log(30.0)), progress=None):
+        """Every group takes `steps` steps; progress(group, step) is called
+        after each.  The first failure of any group is raised here."""
+        errors = []
+        streams = [_group_stream() for _ in self.groups]
+
+        def work(gi):
+            g = self.groups[gi]
+            stream, current = streams[gi]
+            try:
+                with current:
+                    for _ in range(steps):
+                        if errors:
+                            return
+                        g.run_step(bars)
+                        if progress is not None:
+                            progress(gi, g.step)
+                stream.synchronize()
+            except BaseException as e:  # noqa: BLE001 - handed to the caller
+                errors.append(e)
+
+        threads = [threading.Thread(target=work, args=(gi,)) for gi in range(len(self.groups))]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
+
+    @property
+    def ln(self):
+        return np.concatenate([g.ln for g in self.groups])
+
+    @property
+    def J(self):
+        return [J for g in self.groups for J in g.J]
+
+    @property
+    def decisions(self):
+        return sorted(d for g in self.groups for d in g.decisions)
+
+    @property
+    def hard(self):
+        out = {}
+        for g in self.groups:
+            for b, keys in g.hard.items():
+                out.setdefault(b, set()).update(keys)
+        return out
+
+    @property
+    def accepted(self):
+        return sum(g.accepted for g in self.groups)
+
+    @property
+    def pt_seconds(self):
+        return sum(g.pt_seconds for g in self.groups)
+
+    @property
+    def pt_sweeps(self):
+        return sum(g.pt_sweeps for g in self.groups)
+
+    @property
+    def gnn_seconds(self):
+        return self.pool.gnn_seconds
 
 
 class LaoSearch:

@@ -52,3 +52,48 @@ def test_decisions_follow_the_acceptance_rule(mode, direction):
     assert len(run.hard.get(math.log(1.5), set())) <= len(kept)
     if kept:
         assert len(run.hard[math.log(1.5)]) >= 1
+
+
+@pytest.mark.parametrize("mode", ["plain", "random"])
+def test_grouped_search_takes_the_same_decisions(mode):
+    """Chain groups on concurrent streams score each candidate exactly as
+    one launch of all chains does (PT draws are keyed per chain and restart),
+    so the grouped search repeats the single-group search decision for
+    decision."""
+    hs = _gpu()
+    from paper_1605_03607_amd import search as S
+    chains = 6
+    cfg = S.SearchConfig(mode=mode, chains=chains, L=3, restarts=4, K=8, R=2, s_max=4000, proposals=5, top=2)
+    seeds = [workloads.couplings(3, "pm1", 37, c) for c in range(chains)]
+    one = S.Search(cfg, seeds)
+    for _ in range(3):
+        one.run_step(bars=(math.log(1.5),))
+    many = S.GroupedSearch(cfg, seeds, groups=3)
+    many.run(3, bars=(math.log(1.5),))
+    assert many.h0 == one.h0
+    assert many.decisions == sorted(one.decisions)
+    assert np.array_equal(many.ln, one.ln)
+    assert many.hard == one.hard
+
+
+def test_grouped_surrogate_search_runs():
+    hs = _gpu()
+    from paper_1605_03607_amd import search as S
+    chains = 6
+    cfg = S.SearchConfig(mode="surrogate", chains=chains, L=2, restarts=4, K=8, R=2, s_max=3000, proposals=6,
+                         top=2, train_steps=4, train_batch=4)
+    seeds = [workloads.couplings(2, "pm1", 39, c) for c in range(chains)]
+    params = workloads.gnn_params(hs.lib().gnn_param_count(), hs.gnn_fan_ins())
+    many = S.GroupedSearch(cfg, seeds, groups=3, surrogate_params=params)
+    start = many.ln.copy()
+    many.run(3, bars=(math.log(1.5),))
+    assert len(many.decisions) == 3 * chains
+    cur = {ch: start[ch] for ch in range(chains)}
+    for step, ch, ln_cur, ln_new, w, ok in many.decisions:
+        assert ln_cur == cur[ch]
+        assert ok == oracle.rao_accept(ln_cur, ln_new, cfg.t_s, w)
+        if ok:
+            cur[ch] = ln_new
+    assert all(many.ln[ch] == cur[ch] for ch in range(chains))
+    assert many.pool.sur.step == 3 * sum(g.train_steps for g in many.groups)
+    assert np.isfinite(many.pool.sur.params.cpu().numpy()).all()

@@ -1,0 +1,90 @@
+"""Grouped search mechanics on the host: with a stand-in scorer (a fixed
+function of the couplings and the chain index, as PT's ln TTS is for fixed
+seeds), a plain or random-screened search split into concurrent chain groups
+takes exactly the decisions of the single-group search, because every draw
+is keyed by the chain's global index; H0 is the median over all chains."""
+import contextlib
+import hashlib
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+
+def _fake_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed):
+    ln, det = [], []
+    for c in cands:
+        h = hashlib.sha1(np.asarray(c["J"], np.int8).tobytes() + bytes([c["instance_id"] % 251])).digest()
+        ln.append(5.0 + 4.0 * int.from_bytes(h[:4], "little") / 2.0**32)
+        det.append(dict(e_gs=0, confirmed=True, n_censored=0, sweeps_total=100))
+    return np.array(ln), det
+
+
+class _NoStream:
+    def synchronize(self):
+        pass
+
+
+@pytest.fixture
+def S(monkeypatch):
+    import paper_1605_03607_amd as hs
+    hs.lib()
+    from paper_1605_03607_amd import search
+    monkeypatch.setattr(search, "hardness_eval", _fake_eval)
+    monkeypatch.setattr(search, "_group_stream", lambda: (_NoStream(), contextlib.nullcontext()))
+    return search
+
+
+@pytest.mark.parametrize("mode", ["plain", "random"])
+@pytest.mark.parametrize("groups", [2, 3, 7])
+def test_groups_take_the_single_group_decisions(S, mode, groups):
+    chains, steps = 7, 4
+    cfg = S.SearchConfig(mode=mode, chains=chains, L=2, proposals=5, top=2, t_s=0.7)
+    seeds = [workloads.couplings(2, "pm1", 41, c) for c in range(chains)]
+    one = S.Search(cfg, seeds)
+    for _ in range(steps):
+        one.run_step(bars=(math.log(1.2),))
+    many = S.GroupedSearch(cfg, seeds, groups=groups)
+    assert many.h0 == one.h0
+    sizes = [len(g.J) for g in many.groups]
+    assert sum(sizes) == chains and max(sizes) - min(sizes) <= 1 and min(sizes) >= 1
+    seen = []
+    many.run(steps, bars=(math.log(1.2),), progress=lambda g, k: seen.append((g, k)))
+    assert sorted(seen) == [(g, k) for g in range(groups) for k in range(1, steps + 1)]
+    assert many.decisions == sorted(one.decisions)
+    assert np.array_equal(many.ln, one.ln)
+    assert all(np.array_equal(a, b) for a, b in zip(many.J, one.J))
+    assert many.accepted == one.accepted
+    assert many.hard == one.hard
+    assert len(many.decisions) == chains * steps
+
+
+def test_random_screen_is_keyed_by_chain_and_step(S):
+    cfg = S.SearchConfig(mode="random", chains=3, L=2, proposals=6, top=2)
+    seeds = [workloads.couplings(2, "pm1", 43, c) for c in range(3)]
+    run = S.Search(cfg, seeds)
+    picks = [run._random_screen(ch) for ch in range(3)]
+    assert all(len(p) == 2 and len(set(p)) == 2 and all(0 <= x < 6 for x in p) for p in picks)
+    again = S.Search(cfg, seeds[1:], chain_ids=[1, 2], ln=run.ln[1:], h0=run.h0)
+    assert [again._random_screen(ch) for ch in range(2)] == picks[1:]
+
+
+def test_group_failure_reaches_the_caller(S, monkeypatch):
+    cfg = S.SearchConfig(mode="plain", chains=4, L=2)
+    seeds = [workloads.couplings(2, "pm1", 47, c) for c in range(4)]
+    many = S.GroupedSearch(cfg, seeds, groups=2)
+
+    def boom(*a, **k):
+        raise RuntimeError("scorer failed")
+    monkeypatch.setattr(S, "hardness_eval", boom)
+    with pytest.raises(RuntimeError, match="scorer failed"):
+        many.run(2)
+
+
+def test_group_count_is_checked(S):
+    cfg = S.SearchConfig(mode="plain", chains=2, L=2)
+    seeds = [workloads.couplings(2, "pm1", 53, c) for c in range(2)]
+    with pytest.raises(ValueError):
+        S.GroupedSearch(cfg, seeds, groups=3)
