@@ -87,7 +87,7 @@ def parse():
                         "plain / surrogate-screened / random-screened instance search")
     p.add_argument("--search-steps", type=int, default=20)
     p.add_argument("--search-chains", type=int, default=64)
-    p.add_argument("--search-groups", type=int, default=1,
+    p.add_argument("--search-groups", type=int, default=4,
                    help="chain groups stepping concurrently on their own streams (search workloads)")
     p.add_argument("--tau-emcs", type=int, default=20000, help="EMCS of the --workload tau run")
     p.add_argument("--probe", action="store_true",
@@ -425,8 +425,10 @@ def overlap(args):
     mask = np.full(n_words, np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64)
     t1 = time.perf_counter()
     ratios = []
+    by_inst = np.argsort(meta_h[:, 0], kind="stable")  # capture order within each instance
+    bounds = np.searchsorted(meta_h[by_inst, 0], np.arange(n_inst + 1))
     for n in range(n_inst):
-        rows = np.nonzero(meta_h[:, 0] == n)[0]
+        rows = by_inst[bounds[n]:bounds[n + 1]]
         if len(rows) == 0:
             ratios.append(None)
             continue

@@ -277,7 +277,8 @@ int lao_move(int L, const uint8_t *live, int n_loops, uint32_t chain, uint32_t s
  * ground states (1 with one ground state); med_ge = median q over (ground,
  * excited) pairs; ratio = med_ge / med_gg.  has_excited = 0 (and n_ex,
  * med_ge, ratio = 0) with a single level.  Synchronises the stream.
- * HS_EINVAL for bad arguments or n > 46340. */
+ * HS_EINVAL for bad arguments, n > 46340, or n_live other than the mask's
+ * popcount. */
 typedef struct hs_overlap {
     int32_t e0, e1, n_gs, n_ex, has_excited, pad_;
     double med_gg, med_ge, ratio;

@@ -31,11 +31,31 @@ __global__ void __launch_bounds__(256) k_hamming(const uint64_t *configs, int n,
 
 namespace {
 
-double median(std::vector<double> v)
+// Median of the overlaps q(h) = |1 - 2h/n_live| of a multiset of Hamming
+// distances given as counts per distance h = 0..n_live: the distances are
+// visited in ascending order of q, the value itself, so the element(s) found
+// at the middle rank are those a sort of all the pair overlaps would give.
+double median_q(const std::vector<int64_t> &count, int n_live)
 {
-    std::sort(v.begin(), v.end());
-    const size_t m = v.size() / 2;
-    return v.size() % 2 ? v[m] : 0.5 * (v[m - 1] + v[m]);
+    std::vector<double> qv(size_t(n_live) + 1);
+    std::vector<int> order(size_t(n_live) + 1);
+    int64_t total = 0;
+    for (int h = 0; h <= n_live; ++h) {
+        qv[h] = std::fabs(1.0 - 2.0 * double(h) / n_live);
+        order[h] = h;
+        total += count[h];
+    }
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return qv[a] < qv[b]; });
+    auto at = [&](int64_t rank) {  // the element of 0-based rank in ascending order
+        int64_t cum = 0;
+        for (int h : order) {
+            cum += count[h];
+            if (cum > rank) return qv[h];
+        }
+        return qv[order.back()];
+    };
+    const int64_t m = total / 2;
+    return total % 2 ? at(m) : 0.5 * (at(m - 1) + at(m));
 }
 
 }  // namespace
@@ -52,6 +72,14 @@ int overlap_analyze(const uint64_t *configs, const int32_t *energy, int n, int n
         n > 46340 || n_words < 1 || n_live < 1)
         return fail(HS_EINVAL, "overlap_analyze: bad arguments");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // every distance is at most popcount(mask): n_live must be that count
+    std::vector<uint64_t> mh(size_t(n_words), 0);
+    hipError_t em = hipMemcpyAsync(mh.data(), mask, mh.size() * 8, hipMemcpyDeviceToHost, s);
+    if (em == hipSuccess) em = hipStreamSynchronize(s);
+    if (em != hipSuccess) return fail(HS_EHIP, std::string("overlap_analyze: ") + hipGetErrorString(em));
+    int live = 0;
+    for (uint64_t w : mh) live += __builtin_popcountll(w);
+    if (live != n_live) return fail(HS_EINVAL, "overlap_analyze: n_live is not the popcount of the mask");
     hipLaunchKernelGGL(dev::k_hamming, dim3(unsigned(n), unsigned((n + 255) / 256)), dim3(256), 0, s, configs, n,
                        n_words, mask, scratch);
     std::vector<int32_t> h(size_t(n) * size_t(n));
@@ -77,14 +105,13 @@ int overlap_analyze(const uint64_t *configs, const int32_t *energy, int n, int n
         }
         return kept;
     };
-    auto q = [&](int i, int j) { return std::fabs(1.0 - 2.0 * double(h[size_t(i) * n + size_t(j)]) / n_live); };
     const std::vector<int> gs = distinct(lv[0]);
-    std::vector<double> gg;
+    std::vector<int64_t> gg(size_t(n_live) + 1, 0);
     for (size_t a = 0; a < gs.size(); ++a)
-        for (size_t b = a + 1; b < gs.size(); ++b) gg.push_back(q(gs[a], gs[b]));
+        for (size_t b = a + 1; b < gs.size(); ++b) ++gg[h[size_t(gs[a]) * n + size_t(gs[b])]];
     out->e0 = lv[0];
     out->n_gs = int32_t(gs.size());
-    out->med_gg = gg.empty() ? 1.0 : median(gg);
+    out->med_gg = gs.size() < 2 ? 1.0 : median_q(gg, n_live);
     out->has_excited = lv.size() > 1 ? 1 : 0;
     out->e1 = lv.size() > 1 ? lv[1] : lv[0];
     out->n_ex = 0;
@@ -92,11 +119,11 @@ int overlap_analyze(const uint64_t *configs, const int32_t *energy, int n, int n
     out->ratio = 0.0;
     if (lv.size() > 1) {
         const std::vector<int> ex = distinct(lv[1]);
-        std::vector<double> ge;
+        std::vector<int64_t> ge(size_t(n_live) + 1, 0);
         for (int g : gs)
-            for (int x : ex) ge.push_back(q(g, x));
+            for (int x : ex) ++ge[h[size_t(g) * n + size_t(x)]];
         out->n_ex = int32_t(ex.size());
-        out->med_ge = median(ge);
+        out->med_ge = median_q(ge, n_live);
         out->ratio = out->med_ge / out->med_gg;
     }
     return HS_OK;

@@ -117,7 +117,7 @@ class Search:
         # training steps per step in proportion to the chains this search holds
         self.train_steps = max(1, round(cfg.train_steps * len(self.J) / cfg.chains))
         if ln is None:
-            ln = self._score([dict(L=cfg.L, J=J, live=None, instance_id=i) for i, J in zip(self.ids, self.J)])
+            ln = self._score(self._seed_cands())
         self.ln = np.array(ln, np.float64)
         self.h0 = float(np.median(self.ln)) if h0 is None else float(h0)
         self.accepted = 0
@@ -132,13 +132,18 @@ class Search:
     def sur(self):
         return self.pool.sur
 
-    def _score(self, cands):
+    def _seed_cands(self):
+        return [dict(L=self.cfg.L, J=J, live=None, instance_id=i) for i, J in zip(self.ids, self.J)]
+
+    def _score(self, cands, keep=True):
+        """ln TTS of the candidates; keep=True adds them to the replay buffer."""
         c = self.cfg
         t0 = time.perf_counter()
         ln, det = hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
         self.pt_seconds += time.perf_counter() - t0
         self.pt_sweeps += sum(d["sweeps_total"] for d in det)
-        self.pool.add(cands, ln)
+        if keep:
+            self.pool.add(cands, ln)
         return ln
 
     def _proposals(self, chain):
@@ -226,63 +231,94 @@ class Search:
         self.step += 1
 
 
-def _group_stream():
-    """A new stream (default priority) and the context that makes it the
-    calling thread's current one."""
+_STREAMS = []
+
+
+def _group_stream(i):
+    """Stream i (default priority) and the context that makes it the calling
+    thread's current one.  Streams are kept for the process: the caching
+    allocator keeps freed blocks per stream, so a later search reuses the
+    memory of an earlier one instead of allocating afresh while other
+    groups' kernels run."""
     import torch
-    s = torch.cuda.Stream()
-    return s, torch.cuda.stream(s)
+    while len(_STREAMS) <= i:
+        _STREAMS.append(torch.cuda.Stream())
+    return _STREAMS[i], torch.cuda.stream(_STREAMS[i])
+
+
+def _in_groups(n, fn):
+    """fn(i, failed) for i < n, each in a host thread on stream i; failed is
+    set once any call raises, and the first exception is raised here."""
+    errors = []
+    failed = threading.Event()
+    streams = [_group_stream(i) for i in range(n)]
+
+    def work(i):
+        stream, current = streams[i]
+        try:
+            with current:
+                fn(i, failed)
+            stream.synchronize()
+        except BaseException as e:  # noqa: BLE001 - handed to the caller
+            errors.append(e)
+            failed.set()
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(n)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    if errors:
+        raise errors[0]
 
 
 class GroupedSearch:
     """The chains of one search in `groups` contiguous groups that step
     concurrently, each in a host thread with a stream of its own (default
-    priority).  The seeds are scored in one call, so H0 is the median over
-    all chains as in Search.  The attributes mirror Search's, merged over the
+    priority).  Each group scores its own seeds, concurrently; H0 is the
+    median over all chains and the seeds enter the replay buffer in chain
+    order, as in Search.  The attributes mirror Search's, merged over the
     groups; pt_seconds sums the groups' (overlapping) PT calls."""
 
     def __init__(self, cfg, seeds, groups=4, surrogate_params=None):
         n = len(seeds)
         if not 1 <= groups <= n:
             raise ValueError("need 1 <= groups <= chains")
-        head = Search(cfg, seeds, surrogate_params)
         self.cfg = cfg
-        self.pool = head.pool
-        self.h0 = head.h0
-        self.init_pt_seconds = head.pt_seconds
-        self.init_pt_sweeps = head.pt_sweeps
+        self.pool = _Pool(cfg, surrogate_params)
         cuts = [round(g * n / groups) for g in range(groups + 1)]
-        self.groups = [Search(cfg, seeds[a:b], chain_ids=range(a, b), pool=self.pool, ln=head.ln[a:b], h0=head.h0)
+        nan = np.full(n, np.nan)
+        self.groups = [Search(cfg, seeds[a:b], chain_ids=range(a, b), pool=self.pool, ln=nan[a:b], h0=np.nan)
                        for a, b in zip(cuts[:-1], cuts[1:])]
+
+        def score(i, failed):
+            g = self.groups[i]
+            g.ln = np.array(g._score(g._seed_cands(), keep=False), np.float64)
+
+        _in_groups(groups, score)
+        for g in self.groups:
+            self.pool.add(g._seed_cands(), g.ln)
+        self.h0 = float(np.median(self.ln))
+        self.init_pt_seconds = max(g.pt_seconds for g in self.groups)
+        self.init_pt_sweeps = sum(g.pt_sweeps for g in self.groups)
+        for g in self.groups:
+            g.h0 = self.h0
+            g.pt_seconds, g.pt_sweeps = 0.0, 0
 
     def run(self, steps, bars=(math.log(3.0), math.log(10.0), math.log(30.0)), progress=None):
         """Every group takes `steps` steps; progress(group, step) is called
         after each.  The first failure of any group is raised here."""
-        errors = []
-        streams = [_group_stream() for _ in self.groups]
 
-        def work(gi):
-            g = self.groups[gi]
-            stream, current = streams[gi]
-            try:
-                with current:
-                    for _ in range(steps):
-                        if errors:
-                            return
-                        g.run_step(bars)
-                        if progress is not None:
-                            progress(gi, g.step)
-                stream.synchronize()
-            except BaseException as e:  # noqa: BLE001 - handed to the caller
-                errors.append(e)
+        def walk(i, failed):
+            g = self.groups[i]
+            for _ in range(steps):
+                if failed.is_set():
+                    return
+                g.run_step(bars)
+                if progress is not None:
+                    progress(i, g.step)
 
-        threads = [threading.Thread(target=work, args=(gi,)) for gi in range(len(self.groups))]
-        for t in threads:
-            t.start()
-        for t in threads:
-            t.join()
-        if errors:
-            raise errors[0]
+        _in_groups(len(self.groups), walk)
 
     @property
     def ln(self):

@@ -76,3 +76,36 @@ def test_full_buffer_counts_but_stops_writing():
     lanes = sum(d["K"] * d["R"] for d in insts)
     assert count == 4 * lanes
     assert set(meta[:, 0].tolist()) <= {0, 1}
+
+
+@pytest.mark.parametrize("L,n,n_levels,frac_missing", [(3, 300, 3, 0.0), (4, 257, 2, 0.05), (2, 40, 1, 0.0)])
+def test_overlap_summary_of_many_states_matches_oracle(L, n, n_levels, frac_missing):
+    """Many distinct states, repeats and global flips on up to three levels
+    (the medians run over thousands of pairs with many equal overlaps)."""
+    hs, torch = _gpu()
+    N = 8 * L * L
+    g = np.random.default_rng([L, n, n_levels])
+    live = workloads.missing_mask(L, frac_missing, 23, L)
+    live = np.ones(N, np.uint8) if live is None else np.asarray(live, np.uint8)
+    base = g.integers(0, 2, (n // 3 + 1, N), dtype=np.uint8) & live
+    pick = g.integers(0, len(base), n)
+    bits = base[pick].copy()
+    flip = g.random(n) < 0.3
+    bits[flip] ^= live
+    energy = (-40 + 2 * (pick % n_levels)).astype(np.int32)
+    n_words = (N + 63) // 64
+    configs = np.stack([np.pad(hs.pack_sites(b), (0, n_words - len(hs.pack_sites(b)))) for b in bits])
+    mask = np.zeros(n_words, np.uint64)
+    mask[:len(hs.pack_sites(live))] = hs.pack_sites(live)
+    s = hs.overlap_analyze(configs, energy, mask, int(live.sum()))
+    o = O.summary(list(zip(energy.tolist(), bits)), live)
+    for k in ("e0", "e1", "n_gs", "n_ex", "med_gg", "med_ge", "ratio"):
+        assert s[k] == o[k], (k, s[k], o[k])
+
+
+def test_overlap_rejects_a_wrong_live_count():
+    hs, torch = _gpu()
+    configs = np.zeros((2, 1), np.uint64)
+    mask = np.array([np.uint64(0xFF)], np.uint64)
+    with pytest.raises(hs.HardspinError, match="popcount"):
+        hs.overlap_analyze(configs, np.array([0, 1], np.int32), mask, 9)

@@ -33,7 +33,7 @@ def S(monkeypatch):
     hs.lib()
     from paper_1605_03607_amd import search
     monkeypatch.setattr(search, "hardness_eval", _fake_eval)
-    monkeypatch.setattr(search, "_group_stream", lambda: (_NoStream(), contextlib.nullcontext()))
+    monkeypatch.setattr(search, "_group_stream", lambda i: (_NoStream(), contextlib.nullcontext()))
     return search
 
 
