@@ -134,6 +134,40 @@ def cpu_baseline(cfg, insts, budget_s):
                       f"{el:.1f} s wall"}
 
 
+def search_cpu_baseline(cfg, seeds, budget_s, sweeps_per_step):
+    """The CPU oracle's hardness_eval, as it stands, on the host's cores: one
+    seed instance per thread, two restarts each with the sweep cap lowered so
+    the sample fits the budget (the cost per sweep does not depend on the
+    cap), scaled to the seconds one plain search step's PT sweeps take."""
+    import oracle
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16, len(seeds)))
+    t0 = time.perf_counter()
+    r = oracle.hardness_eval(cfg.L, None, seeds[0], 0, cfg.seed, 1, cfg.K, cfg.R, cfg.beta, cfg.swap_interval, 20)
+    per_sweep = (time.perf_counter() - t0) / max(1, int(r["r_sweeps"].sum()))
+    s_cap = int(max(50, min(cfg.s_max, budget_s / per_sweep / 2)))
+    sweeps = [0] * cores
+
+    def work(i):
+        out = oracle.hardness_eval(cfg.L, None, seeds[i], i, cfg.seed, 2, cfg.K, cfg.R, cfg.beta,
+                                   cfg.swap_interval, s_cap)
+        sweeps[i] = int(out["r_sweeps"].sum())
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(cores)]
+    t0 = time.perf_counter()
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    el = time.perf_counter() - t0
+    rate = sum(sweeps) / el
+    return {"value": sweeps_per_step / rate, "unit": "s per plain search step (PT sweeps only)", "cores": cores,
+            "kind": "oracle", "sweeps_per_s": rate,
+            "sample": f"hardness_eval of {cores} seed instances (one per thread), 2 restarts each, "
+                      f"sweep cap {s_cap}: {sum(sweeps)} sweeps in {el:.1f} s wall; scaled to "
+                      f"{sweeps_per_step:.3g} sweeps per plain step"}
+
+
 def uneven(args):
     """1024 instances of mixed size (C4..C12, 2% missing spins, K 24..48):
     the workgroup shape chosen by the autotuner, each step one replay of a
@@ -252,6 +286,10 @@ def search(args):
         "surrogate_over_plain": (rate("surrogate") / rate("plain")) if rate("plain") > 0 else None,
         "arms": arms,
     }
+    if not args.no_cpu_baseline:
+        plain = S.SearchConfig(mode="plain", chains=args.search_chains)
+        out["cpu_baseline"] = search_cpu_baseline(plain, seeds, args.cpu_seconds,
+                                                  arms["plain"]["pt_sweeps"] / args.search_steps)
     print(json.dumps(out), flush=True)
 
 
