@@ -134,14 +134,36 @@ def cpu_baseline(cfg, insts, budget_s):
                       f"{el:.1f} s wall"}
 
 
-def search_cpu_baseline(cfg, seeds, budget_s, sweeps_per_step):
+def host_cores(limit=16):
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return max(1, min(cores, limit))
+
+
+def pt_roofline(attempts, kernel_ms, launches, kernel, wall_s=None):
+    """Roofline object of the sweep kernel from the attempts of `launches`
+    launches and their summed device time (HIP events on the launch
+    streams): algorithmic int32 lane operations per launch over the mean
+    launch duration.  With wall_s, also the whole chip's share over that
+    wall time (launches of concurrent groups overlap, so their durations
+    add up to more than the time they span)."""
+    achieved = attempts * A_OPS / (kernel_ms / 1e3) if kernel_ms > 0 else 0.0
+    out = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
+           "unit": "Tops/s (int32 lane operations)", "frac": achieved / PEAK_INT32_OPS, "traffic": None,
+           "kernel_ms_avg": kernel_ms / max(1, launches), "launches": launches, "ops_per_attempt": A_OPS,
+           "kernel": kernel}
+    if wall_s:
+        out["chip_frac_over_wall"] = attempts * A_OPS / wall_s / PEAK_INT32_OPS
+        out["wall_s"] = wall_s
+    return out
+
+
+def search_cpu_baseline(cfg, seeds, budget_s, sweeps_per_step, what="plain search step"):
     """The CPU oracle's hardness_eval, as it stands, on the host's cores: one
     seed instance per thread, two restarts each with the sweep cap lowered so
     the sample fits the budget (the cost per sweep does not depend on the
-    cap), scaled to the seconds one plain search step's PT sweeps take."""
+    cap), scaled to the seconds one step's PT sweeps take."""
     import oracle
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 16, len(seeds)))
+    cores = min(host_cores(), len(seeds))
     t0 = time.perf_counter()
     r = oracle.hardness_eval(cfg.L, None, seeds[0], 0, cfg.seed, 1, cfg.K, cfg.R, cfg.beta, cfg.swap_interval, 20)
     per_sweep = (time.perf_counter() - t0) / max(1, int(r["r_sweeps"].sum()))
@@ -161,11 +183,59 @@ def search_cpu_baseline(cfg, seeds, budget_s, sweeps_per_step):
         th.join()
     el = time.perf_counter() - t0
     rate = sum(sweeps) / el
-    return {"value": sweeps_per_step / rate, "unit": "s per plain search step (PT sweeps only)", "cores": cores,
+    return {"value": sweeps_per_step / rate, "unit": f"s per {what} (PT sweeps only)", "cores": cores,
             "kind": "oracle", "sweeps_per_s": rate,
             "sample": f"hardness_eval of {cores} seed instances (one per thread), 2 restarts each, "
                       f"sweep cap {s_cap}: {sum(sweeps)} sweeps in {el:.1f} s wall; scaled to "
-                      f"{sweeps_per_step:.3g} sweeps per plain step"}
+                      f"{sweeps_per_step:.3g} sweeps per {what}"}
+
+
+def _products(T, M):
+    """Products g(t) g(t + d) of the autocorrelation sums over lags 0..M of a
+    run of T passes, per configuration."""
+    M = min(M, T - 1)
+    return (M + 1) * T - M * (M + 1) // 2
+
+
+def walk_cpu_baseline(insts, seed, K, R, beta, si, T, max_lag, budget_s):
+    """The CPU oracle's recorded temperature walk and autocorrelation sums,
+    as they stand, on the host's cores: one instance per thread for a prefix
+    of the run (its cost per EMCS is constant), then the sums of one prefix
+    scaled by the count of products to the full run and window.  Returns the
+    seconds per EMCS and per instance's sums on one core, and the sample."""
+    import oracle.walk as W
+    cores = min(host_cores(), len(insts))
+    d = insts[0]
+    t0 = time.perf_counter()
+    W.walk(d["L"], None, d["J"], K, R, beta, 0, seed, si, 2)
+    per_emcs = (time.perf_counter() - t0) / 2
+    n_s = int(max(8, 0.8 * budget_s / per_emcs))
+    trajs = [None] * cores
+
+    def work(i):
+        trajs[i], _ = W.walk(insts[i]["L"], None, insts[i]["J"], K, R, beta, i, seed, si, n_s)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(cores)]
+    t0 = time.perf_counter()
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    el_walk = time.perf_counter() - t0
+    # the sums' cost does not depend on the values: time the first lags of
+    # a full-length run of random indices, scale by the product count
+    traj = np.random.default_rng(7).integers(0, K, (T, K * R)).astype(np.uint8)
+    t0 = time.perf_counter()
+    W.acf_sums(traj, K, 9)
+    m_s = int(min(max_lag, max(9, 10 * 0.15 * budget_s / max(1e-6, time.perf_counter() - t0) - 1)))
+    t0 = time.perf_counter()
+    W.acf_sums(traj, K, m_s)
+    el_acf = time.perf_counter() - t0
+    acf_full = el_acf * _products(T, max_lag) / _products(T, m_s)
+    sample = (f"walk of {cores} C8 instances (one per thread) x {n_s} EMCS in {el_walk:.1f} s wall, scaled to "
+              f"{T} EMCS; sums over the first {m_s + 1} lags of a {T}-pass run in {el_acf:.2f} s, scaled by the "
+              f"product count to {max_lag + 1} lags ({acf_full:.1f} s)")
+    return {"per_emcs": el_walk / n_s, "acf": acf_full, "cores": cores, "sample": sample}
 
 
 def uneven(args):
@@ -266,6 +336,7 @@ def search(args):
             "steps": args.search_steps, "seconds": wall, "s_per_step": wall / args.search_steps,
             "init_seconds": t_init, "pt_seconds": run.pt_seconds, "gnn_seconds": run.gnn_seconds,
             "pt_sweeps": int(run.pt_sweeps), "accepted": run.accepted, "h0_ln_tts": run.h0,
+            "pt_device_ms": run.pt_device_ms, "pt_attempts": int(run.pt_attempts), "pt_calls": run.pt_calls,
             "hard_instances": hard,
             "hard_instances_per_hour": {k: v / hours for k, v in hard.items()},
             "final_median_ln_tts_finite": float(np.median(run.ln[finite])) if finite.any() else None,
@@ -285,6 +356,12 @@ def search(args):
                    "bounded_steps": args.search_steps, "chain_groups": args.search_groups},
         "surrogate_over_plain": (rate("surrogate") / rate("plain")) if rate("plain") > 0 else None,
         "arms": arms,
+        "roofline": pt_roofline(sum(a["pt_attempts"] for a in arms.values()),
+                                sum(a["pt_device_ms"] for a in arms.values()),
+                                sum(a["pt_calls"] for a in arms.values()),
+                                "k_pt_sweep<false> in hardness_eval (stop on agreement), all launches of the "
+                                "three arms; concurrent groups share the chip",
+                                sum(a["seconds"] for a in arms.values())),
     }
     if not args.no_cpu_baseline:
         plain = S.SearchConfig(mode="plain", chains=args.search_chains)
@@ -324,7 +401,13 @@ def search_reverse(args):
                    "bounded_steps": args.search_steps, "chain_groups": args.search_groups},
         "easy_instances": easy, "h0_ln_tts": h0, "final_median_ln_tts": med,
         "median_drop_ln": h0 - med, "accepted": run.accepted, "pt_sweeps": int(run.pt_sweeps),
+        "roofline": pt_roofline(run.pt_attempts, run.pt_device_ms, run.pt_calls,
+                                "k_pt_sweep<false> in hardness_eval (stop on agreement), all launches; "
+                                "concurrent groups share the chip", wall),
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = search_cpu_baseline(cfg, seeds, args.cpu_seconds,
+                                                  run.pt_sweeps / args.search_steps, "reversed search step")
     print(json.dumps(out), flush=True)
 
 
@@ -357,6 +440,7 @@ def tau(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_pt, ms_acf = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    acf_products = n_inst * K * R * _products(T, max_lag)
     taus, ok_i, ok_ii, conv = [], 0, 0, 0
     for n in range(n_inst):
         t_emcs, win, c = hs.walk_tau(acf[n], T)
@@ -376,12 +460,21 @@ def tau(args):
         "config": {"workload": f"tau, {n_inst} C8 instances J=+-1, K{K} R{R} beta 0.1..5.0, EMCS = {si} sweeps + "
                                f"1 exchange, {T} EMCS", "max_lag_emcs": max_lag},
         "pt_attempts_per_s": attempts / (ms_pt / 1e3), "pt_ms": ms_pt, "acf_ms": ms_acf,
+        "roofline": pt_roofline(attempts, ms_pt, 1, "k_pt_sweep<true> (walk recording), one launch"),
+        "acf": {"kernel": "k_walk_acf", "products": acf_products,
+                "int32_lane_ops_per_s": 2 * acf_products / (ms_acf / 1e3),
+                "frac_of_alu_peak": 2 * acf_products / (ms_acf / 1e3) / PEAK_INT32_OPS},
         "tau_sweeps": {"median": float(np.median(taus)), "p90": float(np.percentile(taus, 90)),
                        "max": float(np.max(taus))},
         "window_converged": int(conv), "criterion_hot_half": int(ok_i), "criterion_20_tau": int(ok_ii),
         "energy_mismatches": b.measure(),
     }
     b.close()
+    if not args.no_cpu_baseline:
+        c = walk_cpu_baseline(insts, 2024, K, R, beta, si, T, max_lag, args.cpu_seconds)
+        per_inst = c["per_emcs"] * T + c["acf"]
+        out["cpu_baseline"] = {"value": c["cores"] * 3600.0 / per_inst, "unit": out["unit"], "cores": c["cores"],
+                               "kind": "oracle", "sample": c["sample"]}
     print(json.dumps(out), flush=True)
 
 
@@ -396,6 +489,7 @@ def lao(args):
     t0 = time.perf_counter()
     run = S.LaoSearch(cfg, n_loops=350)
     t_init = time.perf_counter() - t0
+    sweeps0 = run.pt_sweeps
     t0 = time.perf_counter()
     for k in range(args.search_steps):
         run.run_step()
@@ -418,7 +512,13 @@ def lao(args):
         "initial_mean_ln_tts": float(np.mean(run.ln0)), "final_mean_ln_tts": float(np.mean(run.ln)),
         "accepted": run.accepted, "scored": run.scored, "pt_ground_state_equals_planted": run.gs_found,
         "init_seconds": t_init, "pt_seconds": run.pt_seconds, "pt_sweeps": int(run.pt_sweeps),
+        "roofline": pt_roofline(run.pt_attempts, run.pt_device_ms, run.pt_calls,
+                                "k_pt_sweep<false> in hardness_eval (stop on agreement), all launches",
+                                t_init + wall),
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = search_cpu_baseline(cfg, [i["J"] for i in run.inst], args.cpu_seconds,
+                                                  (run.pt_sweeps - sweeps0) / args.search_steps, "LAO step")
     print(json.dumps(out), flush=True)
 
 
@@ -441,8 +541,12 @@ def overlap(args):
              for n in range(n_inst)]
     b = hs.PTBatch(insts, 3033, swap_interval=si)
     walk = torch.zeros((n_inst, T, 64), dtype=torch.uint8, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e0.record()
     b.sweep_record(T * si, walk)
+    e1.record()
     acf, hot = hs.walk_autocorr(walk, T, K, R, max_lag)
     del walk
     taus = [hs.walk_tau(acf[n], T) for n in range(n_inst)]
@@ -462,7 +566,7 @@ def overlap(args):
     meta_h = meta[:n_cap].cpu().numpy()
     mask = np.full(n_words, np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64)
     t1 = time.perf_counter()
-    ratios = []
+    ratios, analysed = [], []
     by_inst = np.argsort(meta_h[:, 0], kind="stable")  # capture order within each instance
     bounds = np.searchsorted(meta_h[by_inst, 0], np.arange(n_inst + 1))
     for n in range(n_inst):
@@ -474,6 +578,7 @@ def overlap(args):
         key = np.concatenate([meta_h[rows, 2:3].astype(np.uint64), cfg_h[rows]], axis=1)
         _, first = np.unique(key, axis=0, return_index=True)
         sel = rows[np.sort(first)][:2000]
+        analysed.append(len(sel))
         s = hs.overlap_analyze(cfg_h[sel], meta_h[sel, 2], mask, 8 * L * L)
         ratios.append(s["ratio"])
     t_ov = time.perf_counter() - t1
@@ -497,9 +602,38 @@ def overlap(args):
         "tau_converged": int(sum(t[2] for t in taus)),
         "spearman_tau_vs_ratio": rho, "pairs": len(pairs),
         "pt_seconds": t_pt, "overlap_seconds": t_ov,
+        "roofline": pt_roofline(n_inst * K * R * 8 * L * L * T * si, e0.elapsed_time(e1), 1,
+                                "k_pt_sweep<true> (walk recording), the walk launch"),
     }
     b.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = overlap_cpu_baseline(insts, K, R, beta, si, T, max_lag, n_snap,
+                                                   float(np.mean(analysed)) if analysed else 0.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def overlap_cpu_baseline(insts, K, R, beta, si, T, max_lag, n_snap, n_analysed, budget_s):
+    """The CPU oracle on the overlap workload, as it stands: the walk and its
+    sums (walk_cpu_baseline) plus the snapshot EMCS at the walk's cost per
+    EMCS, and the oracle's overlap summary timed on 120 synthetic
+    configurations of two levels and scaled by the pair count to the mean
+    number analysed per instance here (the snapshot capture itself is not
+    counted); seconds for all instances over the host's cores."""
+    import oracle.overlap as O
+    c = walk_cpu_baseline(insts, 3033, K, R, beta, si, T, max_lag, 0.7 * budget_s)
+    N = 8 * insts[0]["L"] ** 2
+    g = np.random.default_rng(5)
+    n_s = 120
+    cfgs = [(int(-700 + 4 * (i % 2)), g.integers(0, 2, N, dtype=np.uint8)) for i in range(n_s)]
+    t0 = time.perf_counter()
+    O.summary(cfgs)
+    el = time.perf_counter() - t0
+    summ = el * (n_analysed / n_s) ** 2
+    per_inst = c["per_emcs"] * (T + n_snap) + c["acf"] + summ
+    return {"value": len(insts) * per_inst / c["cores"], "unit": "s per workload", "cores": c["cores"],
+            "kind": "oracle",
+            "sample": c["sample"] + f"; summary of {n_s} configurations in {el:.2f} s, scaled to "
+                                    f"{n_analysed:.0f} per instance ({summ:.1f} s)"}
 
 
 def surrogate(args):
@@ -541,8 +675,38 @@ def surrogate(args):
     res = {"metric": "surrogate step time (C8 graphs)", "value": out["train"]["ms"], "unit": "ms per training step",
            "n_gpus": 1, "steps": 20, "warmup": 2, "higher_is_better": False, "dtype": "bf16 (fp32 accumulate)",
            "data": "synthetic", "config": {"workload": "surrogate, 16-graph training batch, 1024-graph screen"},
-           "detail": out, "mfma_peak_tflops_bf16": 2500.0}
+           "detail": out, "mfma_peak_tflops_bf16": 2500.0,
+           "roofline": {"bound": "mfma", "achieved": out["train"]["tflops"], "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": out["train"]["tflops"] / 2500.0, "traffic": None,
+                        "kernel": "training step (all of its kernels: rows, gathers, weight gradients, Adam); "
+                                  "matrix-product FLOPs over the step's time",
+                        "kernel_ms_avg": out["train"]["ms"]}}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = surrogate_cpu_baseline(n_par, L, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def surrogate_cpu_baseline(n_par, L, budget_s):
+    """The CPU oracle's surrogate (fp64 numpy, as it stands): training steps
+    (loss, gradient, Adam) on the same 16-graph batch shape, for about the
+    budget; ms per training step on one process."""
+    import oracle.gnn as G
+
+    import paper_1605_03607_amd as hs
+    theta = workloads.gnn_params(n_par, hs.gnn_fan_ins()).astype(np.float64)
+    B = G.batch([(L, None, workloads.couplings(L, "pm7", 99, g)) for g in range(16)])
+    labels = np.linspace(5.0, 12.0, 16)
+    m, v = np.zeros_like(theta), np.zeros_like(theta)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        _, grad = G.loss_and_grad(theta, B, labels)[:2]
+        theta, m, v = G.adam(theta, m, v, grad, steps + 1, 3e-3)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 200:
+            break
+    return {"value": el * 1e3 / steps, "unit": "ms per training step", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} training steps of 16 C8 graphs in {el:.1f} s (numpy fp64, one process)"}
 
 
 def main():

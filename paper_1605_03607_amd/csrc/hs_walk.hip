@@ -12,43 +12,74 @@
 namespace hs {
 namespace dev {
 
-constexpr int kLagTile = 64;    // lags per workgroup (16 per thread, 4 lag phases)
-constexpr int kTimeTile = 256;  // passes per LDS tile
+constexpr int kLagTile = 64;    // lags per workgroup: 4 runs of 16 consecutive lags
+constexpr int kTimeTile = 256;  // passes per LDS tile (a multiple of 4)
+constexpr int kBaseW = kTimeTile / 4 + 1;                 // words per configuration row (odd: no bank clash)
+constexpr int kShiftW = (kTimeTile + kLagTile) / 4 + 1;   // the lag window needs one word past the tile
 
-// Workgroup (n, lag tile): 256 threads = 64 configurations x 4 lag phases;
-// thread (j, c) sums lags d0 + j + 4 i, i < 16.  Each tile stages the centred
-// indices g of passes [t0, t0 + kTimeTile) and [t0 + d0, t0 + d0 + kTimeTile
-// + kLagTile) as int8 (|g| <= 63; zero beyond the run and for dead
-// configurations), so every product reads LDS only.
+// Centred index g = 2 k - (K - 1) as a byte (|g| <= 63); 0 past the run and
+// for configurations beyond K R.
+__device__ __forceinline__ uint32_t g_byte(const uint8_t *src, int64_t t, int64_t T, int cc, int C, int K)
+{
+    if (t >= T || cc >= C) return 0u;
+    return uint32_t(uint8_t(int8_t(2 * int(src[t * 64 + cc]) - (K - 1))));
+}
+
+// Workgroup (n, lag tile): 256 threads = 64 configurations x 4 runs of 16
+// lags; thread (c, j) sums lags d = d0 + 16 j + i, i < 16.  A tile stages,
+// per configuration row, g of passes [t0, t0 + kTimeTile) (base) and
+// [t0 + d0, t0 + d0 + kTimeTile + kLagTile + 4) (shifted) packed four passes
+// to a word (byte b of word w = pass 4 w + b).  For four passes t .. t + 3
+// the products g(t + u) g(t + u + d) of one lag are one 4-way signed byte
+// dot product of the base word and the shifted bytes at offset t + d,
+// aligned out of two neighbouring words; a window of five shifted words
+// serves the 16 lags and slides by one word per four passes.
 __global__ void __launch_bounds__(256) k_walk_acf(const uint8_t *walk, int64_t cap, int64_t T, int K, int C,
                                                   int max_lag, int64_t *acf)
 {
-    __shared__ int8_t base[kTimeTile * 64];
-    __shared__ int8_t shifted[(kTimeTile + kLagTile) * 64];
+    __shared__ uint32_t base[64 * kBaseW];
+    __shared__ uint32_t shifted[64 * kShiftW];
     const int n = blockIdx.x;
     const int d0 = blockIdx.y * kLagTile;
     const int c = threadIdx.x & 63, j = threadIdx.x >> 6;
     const uint8_t *src = walk + int64_t(n) * cap * 64;
-    auto gval = [&](int64_t t, int cc) -> int8_t {
-        if (t >= T || cc >= C) return 0;
-        return int8_t(2 * int(src[t * 64 + cc]) - (K - 1));
-    };
     int64_t acc[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0;
     for (int64_t t0 = 0; t0 < T - d0; t0 += kTimeTile) {
         __syncthreads();
-        for (int i = threadIdx.x; i < kTimeTile * 64; i += 256) base[i] = gval(t0 + (i >> 6), i & 63);
-        for (int i = threadIdx.x; i < (kTimeTile + kLagTile) * 64; i += 256)
-            shifted[i] = gval(t0 + d0 + (i >> 6), i & 63);
+        // lane c of each wavefront reads configuration c: 64-byte rows of the walk
+        for (int w = j; w < kTimeTile / 4; w += 4) {
+            const int64_t t = t0 + 4 * w;
+            base[c * kBaseW + w] = g_byte(src, t, T, c, C, K) | (g_byte(src, t + 1, T, c, C, K) << 8) |
+                                   (g_byte(src, t + 2, T, c, C, K) << 16) | (g_byte(src, t + 3, T, c, C, K) << 24);
+        }
+        for (int w = j; w < kShiftW; w += 4) {
+            const int64_t t = t0 + d0 + 4 * w;
+            shifted[c * kShiftW + w] = g_byte(src, t, T, c, C, K) | (g_byte(src, t + 1, T, c, C, K) << 8) |
+                                       (g_byte(src, t + 2, T, c, C, K) << 16) |
+                                       (g_byte(src, t + 3, T, c, C, K) << 24);
+        }
         __syncthreads();
         int32_t part[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) part[i] = 0;
-        for (int t = 0; t < kTimeTile; ++t) {
-            const int32_t gb = base[t * 64 + c];
+        const uint32_t *brow = base + c * kBaseW;
+        const uint32_t *srow = shifted + c * kShiftW + 4 * j;
+        uint32_t win[5];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) part[i] += gb * int32_t(shifted[(t + j + 4 * i) * 64 + c]);
+        for (int k = 0; k < 4; ++k) win[k] = srow[k];
+#pragma unroll 4
+        for (int q = 0; q < kTimeTile / 4; ++q) {
+            win[4] = srow[q + 4];
+            const int32_t b = int32_t(brow[q]);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t h = (i & 3) == 0 ? win[i >> 2] : __builtin_amdgcn_alignbyte(win[(i >> 2) + 1], win[i >> 2], i & 3);
+                part[i] = __builtin_amdgcn_sdot4(b, int32_t(h), part[i], false);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) win[k] = win[k + 1];
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[i] += part[i];
@@ -59,7 +90,7 @@ __global__ void __launch_bounds__(256) k_walk_acf(const uint8_t *walk, int64_t c
         int64_t v = acc[i];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        const int d = d0 + j + 4 * i;
+        const int d = d0 + 16 * j + i;
         if (c == 0 && d <= max_lag) acf[int64_t(n) * (max_lag + 1) + d] = v;
     }
 }

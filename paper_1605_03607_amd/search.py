@@ -49,6 +49,20 @@ ALPHABET_PM7 = np.array([-7, -6, -5, -4, -3, -2, -1, 1, 2, 3, 4, 5, 6, 7], np.in
 ALPHABET_PM1 = np.array([-1, 1], np.int8)  # Algorithm 1's sign flips
 
 
+def _timed_hardness(cands, c):
+    """hardness_eval on the calling thread's current stream, with the device
+    span of the call from events recorded on that stream: (ln, details, ms,
+    spin-flip attempts)."""
+    import torch
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    ln, det = hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
+    end.record()
+    end.synchronize()
+    lanes_sites = c.K * c.R * 8 * c.L * c.L
+    return ln, det, start.elapsed_time(end), sum(d["sweeps_total"] for d in det) * lanes_sites
+
+
 def _geometric(lo, hi, k):
     return lo * (hi / lo) ** (np.arange(k) / (k - 1))
 
@@ -113,6 +127,9 @@ class Search:
         self.step = 0
         self.pt_seconds = 0.0
         self.pt_sweeps = 0
+        self.pt_device_ms = 0.0   # summed device spans of the hardness_eval calls
+        self.pt_attempts = 0      # spin-flip attempts they made
+        self.pt_calls = 0
         self.pool = _Pool(cfg, surrogate_params) if pool is None else pool
         # training steps per step in proportion to the chains this search holds
         self.train_steps = max(1, round(cfg.train_steps * len(self.J) / cfg.chains))
@@ -139,9 +156,12 @@ class Search:
         """ln TTS of the candidates; keep=True adds them to the replay buffer."""
         c = self.cfg
         t0 = time.perf_counter()
-        ln, det = hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
+        ln, det, ms, att = _timed_hardness(cands, c)
         self.pt_seconds += time.perf_counter() - t0
         self.pt_sweeps += sum(d["sweeps_total"] for d in det)
+        self.pt_device_ms += ms
+        self.pt_attempts += att
+        self.pt_calls += 1
         if keep:
             self.pool.add(cands, ln)
         return ln
@@ -303,7 +323,7 @@ class GroupedSearch:
         self.init_pt_sweeps = sum(g.pt_sweeps for g in self.groups)
         for g in self.groups:
             g.h0 = self.h0
-            g.pt_seconds, g.pt_sweeps = 0.0, 0
+            g.pt_seconds, g.pt_sweeps, g.pt_device_ms, g.pt_attempts, g.pt_calls = 0.0, 0, 0.0, 0, 0
 
     def run(self, steps, bars=(math.log(3.0), math.log(10.0), math.log(30.0)), progress=None):
         """Every group takes `steps` steps; progress(group, step) is called
@@ -353,6 +373,18 @@ class GroupedSearch:
         return sum(g.pt_sweeps for g in self.groups)
 
     @property
+    def pt_device_ms(self):
+        return sum(g.pt_device_ms for g in self.groups)
+
+    @property
+    def pt_attempts(self):
+        return sum(g.pt_attempts for g in self.groups)
+
+    @property
+    def pt_calls(self):
+        return sum(g.pt_calls for g in self.groups)
+
+    @property
     def gnn_seconds(self):
         return self.pool.gnn_seconds
 
@@ -377,6 +409,9 @@ class LaoSearch:
         self.step = 0
         self.pt_seconds = 0.0
         self.pt_sweeps = 0
+        self.pt_device_ms = 0.0
+        self.pt_attempts = 0
+        self.pt_calls = 0
         self.scored = 0
         self.gs_found = 0
         self.accepted = 0
@@ -388,10 +423,13 @@ class LaoSearch:
     def _score(self, cands):
         c = self.cfg
         t0 = time.perf_counter()
-        ln, det = hardness_eval([dict(L=c.L, J=J, live=None, instance_id=self.chain_id[ch]) for ch, J, _ in cands],
-                                c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
+        ln, det, ms, att = _timed_hardness(
+            [dict(L=c.L, J=J, live=None, instance_id=self.chain_id[ch]) for ch, J, _ in cands], c)
         self.pt_seconds += time.perf_counter() - t0
         self.pt_sweeps += sum(d["sweeps_total"] for d in det)
+        self.pt_device_ms += ms
+        self.pt_attempts += att
+        self.pt_calls += 1
         for (_, _, e_gs), d in zip(cands, det):
             self.scored += 1
             self.gs_found += int(d["e_gs"] == e_gs)

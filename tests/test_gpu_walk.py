@@ -54,13 +54,15 @@ def test_recorded_walk_matches_oracle_and_sweeps_are_unchanged():
     ref.close()
 
 
-@pytest.mark.parametrize("T,max_lag", [(3000, 300), (257, 64), (40, 100), (0, 5)])
-def test_autocorrelation_sums_are_exact(T, max_lag):
+@pytest.mark.parametrize("T,max_lag,K,R", [(3000, 300, 32, 2), (257, 64, 32, 2), (40, 100, 32, 2), (0, 5, 32, 2),
+                                           (1031, 131, 6, 4), (515, 77, 16, 1), (3, 70, 64, 1)])
+def test_autocorrelation_sums_are_exact(T, max_lag, K, R):
     """Synthetic walks spanning several time tiles and lag tiles with ragged
-    ends, a lag range past the run, and an empty run."""
+    ends, a lag range past the run, an empty run, and fewer than 64
+    configurations (the rest of each 64-byte row is ignored)."""
     hs, torch = _gpu()
     rng = np.random.default_rng(T + max_lag)
-    K, R, cap, n_inst = 32, 2, max(T, 1) + 3, 5
+    cap, n_inst = max(T, 1) + 3, 5
     host = rng.integers(0, K, size=(n_inst, cap, 64)).astype(np.uint8)
     walk = torch.from_numpy(host).cuda()
     acf, hot = hs.walk_autocorr(walk, T, K, R, max_lag)

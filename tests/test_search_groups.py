@@ -34,6 +34,11 @@ def S(monkeypatch):
     from paper_1605_03607_amd import search
     monkeypatch.setattr(search, "hardness_eval", _fake_eval)
     monkeypatch.setattr(search, "_group_stream", lambda i: (_NoStream(), contextlib.nullcontext()))
+
+    def untimed(cands, c):  # the scorer without device events
+        ln, det = search.hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
+        return ln, det, 0.0, 0
+    monkeypatch.setattr(search, "_timed_hardness", untimed)
     return search
 
 
