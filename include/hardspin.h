@@ -297,7 +297,9 @@ int overlap_analyze(const uint64_t *configs, const int32_t *energy, int n, int n
  * ground state, as Appendix B defines the time-to-solution (run time until
  * the lowest energy has been found n+1 times, divided by n+1); Sec. III.B
  * cross-checks ground-state energies by agreement.  detail->n_censored =
- * restarts that ended above E_gs.  Requires R >= 2.  Blocks until done. */
+ * restarts that ended above E_gs.  restart_sweeps (optional, host int64
+ * [n][n_restarts], NULL to leave out) receives t_rho of every restart.
+ * Requires R >= 2.  Blocks until done. */
 typedef struct hs_hardness_params {
     int32_t n_restarts;
     int32_t K;
@@ -307,6 +309,7 @@ typedef struct hs_hardness_params {
     int64_t s_max;
     uint32_t seed;
     int32_t block_waves; /* 0 = tuner */
+    int64_t *restart_sweeps;
 } hs_hardness_params;
 
 typedef struct hs_tts_detail {

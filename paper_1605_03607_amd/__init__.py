@@ -53,7 +53,7 @@ class hs_mutation(C.Structure):
 class hs_hardness_params(C.Structure):
     _fields_ = [("n_restarts", C.c_int32), ("K", C.c_int32), ("R", C.c_int32),
                 ("beta", C.c_void_p), ("swap_interval", C.c_int32), ("s_max", C.c_int64),
-                ("seed", C.c_uint32), ("block_waves", C.c_int32)]
+                ("seed", C.c_uint32), ("block_waves", C.c_int32), ("restart_sweeps", C.c_void_p)]
 
 
 class hs_gnn_batch(C.Structure):
@@ -392,12 +392,14 @@ def rao_accept(ln_cur, ln_new, t_s, w):
 
 def hardness_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed, block_waves=0,
                   stream=None):
-    """ln TTS per candidate (dicts with L, J, live, instance_id) plus details."""
+    """ln TTS per candidate (dicts with L, J, live, instance_id) plus details
+    (restart_sweeps: the sweeps t of every restart)."""
     torch = _torch()
     hi = _HostInstances([dict(c, K=K, R=R, beta=beta) for c in cands])
     beta_arr = np.ascontiguousarray(beta, np.float64)
+    rs = np.zeros((max(1, len(cands)), n_restarts), np.int64)
     p = hs_hardness_params(n_restarts, K, R, beta_arr.ctypes.data, swap_interval, s_max, seed,
-                           block_waves)
+                           block_waves, rs.ctypes.data)
     nb = C.c_size_t(0)
     _check(lib().hardness_workspace_bytes(hi.arr, len(cands), C.byref(p), C.byref(nb)))
     scratch = torch.zeros(max(16, nb.value), dtype=torch.uint8, device="cuda")
@@ -406,7 +408,8 @@ def hardness_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed, blo
     _check(lib().hardness_eval(hi.arr, len(cands), C.byref(p), C.c_void_p(scratch.data_ptr()),
                                nb.value, ln.ctypes.data, det, _stream_ptr(stream)))
     details = [dict(e_gs=det[i].e_gs, confirmed=bool(det[i].confirmed),
-                    n_censored=det[i].n_censored, sweeps_total=det[i].sweeps_total)
+                    n_censored=det[i].n_censored, sweeps_total=det[i].sweeps_total,
+                    restart_sweeps=rs[i].copy())
                for i in range(len(cands))]
     return ln, details
 

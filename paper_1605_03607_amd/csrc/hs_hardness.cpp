@@ -155,6 +155,7 @@ int hardness_eval(const hs_instance *cands, int n, const hs_hardness_params *p, 
         for (int rho = 0; rho < nr; ++rho) {
             const size_t run = size_t(c) * nr + rho;
             sweeps += t[run];
+            if (p->restart_sweeps) p->restart_sweeps[size_t(c) * nr + rho] = t[run];
             int sets = 0;
             for (int r = 0; r < R; ++r) sets += emin[run * 64 + r] == gs ? 1 : 0;
             if (sets >= 2) double_hit = 1;

@@ -215,6 +215,7 @@ def test_hardness_eval_matches_oracle():
         assert det[n]["e_gs"] == o["e_gs"]
         assert det[n]["confirmed"] == o["confirmed"]
         assert det[n]["sweeps_total"] == int(o["r_sweeps"].sum())
+        assert np.array_equal(det[n]["restart_sweeps"], o["r_sweeps"])
         assert (ln[n] == o["ln_tts"]) or (np.isinf(ln[n]) and np.isinf(o["ln_tts"]))
 
 
