@@ -164,8 +164,11 @@ __global__ void __launch_bounds__(256) k_rows(int rows, Seg X, const uint16_t *W
 
 // ---------------------------------------------------------------------------
 // Weight gradient: gW[o][k] += sum_r dZ[r][o] X[r][k], o < 64, k < 64 NSEG,
-// over the rows of this workgroup (kRowsPerBlock, 32 per step).
-constexpr int kRowsPerBlock = 512;
+// over the rows of this workgroup (kRowsPerBlock, 32 per step), added to gW
+// with one atomic per element and workgroup.  Fewer rows per workgroup fill
+// more CUs but add atomics to the same addresses; 256 was the fastest of
+// 128..1024 for C8 batches.
+constexpr int kRowsPerBlock = 256;
 
 template <int NSEG>
 __global__ void __launch_bounds__(256) k_wgrad(int rows, const uint16_t *dZ, Seg X, float *gW)
@@ -238,19 +241,34 @@ __global__ void __launch_bounds__(256) k_wgrad(int rows, const uint16_t *dZ, Seg
 
 // ---------------------------------------------------------------------------
 // Message sums S_v = bf16(sum of M over the edges into v); the edges into v
-// are the reverses (e ^ 1) of its out-edges.
+// are the reverses (e ^ 1) of its out-edges.  One thread per node and 8
+// features (16-byte loads and store); each feature is summed over the
+// out-edge slots in order.
 __global__ void k_gather_sum(const uint16_t *M, const int32_t *outE, uint16_t *S, int nn)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= int64_t(nn) * D) return;
-    const int64_t v = i / D;
-    const int d = int(i % D);
-    float s = 0.f;
+    if (i >= int64_t(nn) * (D / 8)) return;
+    const int64_t v = i / (D / 8);
+    const int c = int(i % (D / 8));
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int j = 0; j < 6; ++j) {
         const int e = outE[v * 6 + j];
-        if (e >= 0) s += bf2f(M[int64_t(e ^ 1) * D + d]);
+        if (e >= 0) {
+            const uint4 w = *reinterpret_cast<const uint4 *>(M + int64_t(e ^ 1) * D + c * 8);
+            const uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s[2 * k] += bf2f(uint16_t(u[k] & 0xFFFFu));
+                s[2 * k + 1] += bf2f(uint16_t(u[k] >> 16));
+            }
+        }
     }
-    S[i] = f2bf(s);
+    uint4 o;
+    o.x = uint32_t(f2bf(s[0])) | (uint32_t(f2bf(s[1])) << 16);
+    o.y = uint32_t(f2bf(s[2])) | (uint32_t(f2bf(s[3])) << 16);
+    o.z = uint32_t(f2bf(s[4])) | (uint32_t(f2bf(s[5])) << 16);
+    o.w = uint32_t(f2bf(s[6])) | (uint32_t(f2bf(s[7])) << 16);
+    *reinterpret_cast<uint4 *>(S + v * D + c * 8) = o;
 }
 
 // One workgroup (256 threads) per graph: mean of the live h rows, y_hat.
@@ -325,7 +343,10 @@ __global__ void k_readout_bwd(const float *dy, const float *P, const float *live
 // dZ = dY * (Z > 0) as bfloat16, and the bias gradient (float).  For edges
 // dY = dM (from the layer above, column 128.. of its input gradient; none
 // for the top layer) + dS of the edge's destination (column 64.. of the node
-// input gradient).
+// input gradient).  Each workgroup adds its 64 bias sums atomically, so the
+// grid is capped: every workgroup adds to the same 64 addresses, and 2048
+// workgroups spent most of the kernel queued on them.
+constexpr unsigned kReluBlocks = 384;
 __global__ void __launch_bounds__(256) k_relu_bwd(int rows, const float *dY, int ldY, int offY, const float *dS,
                                                   const int32_t *dst, const float *Z, uint16_t *dZb, float *gb)
 {
@@ -520,8 +541,10 @@ Bufs views(const Layout &o, void *ws)
 
 unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) / per); }
 
-// Forward pass into the workspace (y_hat in v.y, also copied to y_out if given).
-int forward_pass(const float *P, const Layout &o, const Bufs &v, hipStream_t st)
+// Forward pass into the workspace (y_hat in v.y).  keep_z: also store the
+// float pre-activations the backward pass needs (a forward-only call skips
+// those writes).
+int forward_pass(const float *P, const Layout &o, const Bufs &v, hipStream_t st, bool keep_z)
 {
     hipLaunchKernelGGL(k_cast_weights, dim3(48, kLayers), dim3(256), 0, st, P, v.wb);
     hipLaunchKernelGGL(k_embed, dim3(blocks_for((o.nn + o.nq) * D, 256)), dim3(256), 0, st, P, v.xn, v.xe,
@@ -531,12 +554,12 @@ int forward_pass(const float *P, const Layout &o, const Bufs &v, hipStream_t st)
         const float *Ls = P + kLayer0 + l * kLayerSize;
         Seg xe{{v.H[l], v.H[l], v.M[l]}, {v.src, v.dst, nullptr}};
         hipLaunchKernelGGL((k_rows<3, 4>), dim3(blocks_for(ne, 64)), dim3(256), 0, st, ne, xe, v.wb.wm[l],
-                           Ls + kBm, v.Zm[l], v.M[l + 1]);
-        hipLaunchKernelGGL(k_gather_sum, dim3(blocks_for(o.nn * D, 256)), dim3(256), 0, st, v.M[l + 1], v.outE,
-                           v.S[l], nn);
+                           Ls + kBm, keep_z ? v.Zm[l] : nullptr, v.M[l + 1]);
+        hipLaunchKernelGGL(k_gather_sum, dim3(blocks_for(o.nn * (D / 8), 256)), dim3(256), 0, st, v.M[l + 1],
+                           v.outE, v.S[l], nn);
         Seg xn{{v.H[l], v.S[l], nullptr}, {nullptr, nullptr, nullptr}};
         hipLaunchKernelGGL((k_rows<2, 4>), dim3(blocks_for(nn, 64)), dim3(256), 0, st, nn, xn, v.wb.wh[l],
-                           Ls + kBh, v.Zh[l], v.H[l + 1]);
+                           Ls + kBh, keep_z ? v.Zh[l] : nullptr, v.H[l + 1]);
     }
     hipLaunchKernelGGL(k_readout, dim3(o.G), dim3(256), 0, st, v.H[kLayers], v.live, v.nlive, P, v.mean, v.y,
                        o.N);
@@ -641,7 +664,7 @@ int gnn_forward(const float *params, int32_t n_graphs, int32_t L, void *workspac
     if (rc) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const Bufs v = views(o, workspace);
-    rc = forward_pass(params, o, v, st);
+    rc = forward_pass(params, o, v, st, false);
     if (rc) return rc;
     const hipError_t e = hipMemcpyAsync(y_hat, v.y, size_t(o.G) * 4, hipMemcpyDeviceToDevice, st);
     return e == hipSuccess ? HS_OK : hip_err(e, "gnn_forward: copy");
@@ -660,7 +683,7 @@ int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labe
     if (rc) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const Bufs v = views(o, workspace);
-    rc = forward_pass(params, o, v, st);
+    rc = forward_pass(params, o, v, st, true);
     if (rc) return rc;
     const int ne = int(o.ne), nn = int(o.nn);
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(kParams, 256)), dim3(256), 0, st, grad, int64_t(kParams), 0.f);
@@ -672,7 +695,7 @@ int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labe
     for (int l = kLayers - 1; l >= 0; --l) {
         float *gl = grad + kLayer0 + l * kLayerSize;
         // node update
-        hipLaunchKernelGGL(k_relu_bwd, dim3(std::min<unsigned>(blocks_for(nn, 4), 1024)), dim3(256), 0, st, nn,
+        hipLaunchKernelGGL(k_relu_bwd, dim3(std::min<unsigned>(blocks_for(nn, 4), kReluBlocks)), dim3(256), 0, st, nn,
                            v.dH, D, 0, nullptr, nullptr, v.Zh[l], v.dZ, gl + kBh);
         Seg xn{{v.H[l], v.S[l], nullptr}, {nullptr, nullptr, nullptr}};
         hipLaunchKernelGGL(k_wgrad<2>, dim3(blocks_for(nn, kRowsPerBlock)), dim3(256), 0, st, nn, v.dZ, xn,
@@ -681,7 +704,7 @@ int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labe
         hipLaunchKernelGGL((k_rows<1, 8>), dim3(blocks_for(nn, 64)), dim3(256), 0, st, nn, dzn, v.wb.whT[l],
                            nullptr, v.dXn, nullptr);
         // edge update
-        hipLaunchKernelGGL(k_relu_bwd, dim3(std::min<unsigned>(blocks_for(ne, 4), 2048)), dim3(256), 0, st, ne,
+        hipLaunchKernelGGL(k_relu_bwd, dim3(std::min<unsigned>(blocks_for(ne, 4), kReluBlocks)), dim3(256), 0, st, ne,
                            dXe_above, 192, 128, v.dXn, v.dst, v.Zm[l], v.dZ, gl + kBm);
         Seg xe{{v.H[l], v.H[l], v.M[l]}, {v.src, v.dst, nullptr}};
         hipLaunchKernelGGL(k_wgrad<3>, dim3(blocks_for(ne, kRowsPerBlock)), dim3(256), 0, st, ne, v.dZ, xe,
