@@ -157,6 +157,42 @@ def pt_roofline(attempts, kernel_ms, launches, kernel, wall_s=None):
     return out
 
 
+def mixed_cpu_baseline(insts, seed, swap_interval, budget_s):
+    """The CPU oracle, as it stands, on a mixed batch: one instance per
+    host thread, taken evenly across the batch (each with its own size,
+    missing spins and ladder), a prefix of the sweeps sized to the budget
+    from the slowest of them; live spin-flip attempts per second."""
+    import oracle
+    cores = min(host_cores(), len(insts))
+    pick = [insts[(i * len(insts)) // cores] for i in range(cores)]
+    per_sweep = 0.0
+    for d in pick:
+        st = oracle.pt_init(d["L"], d["live"], d["J"], d["K"], d["R"], d["instance_id"], seed)
+        t0 = time.perf_counter()
+        oracle.pt_run(d["L"], d["live"], d["J"], d["K"], d["R"], d["beta"], d["instance_id"], seed,
+                      swap_interval, 2, st)
+        per_sweep = max(per_sweep, (time.perf_counter() - t0) / 2)
+    sweeps = max(5, int(budget_s / per_sweep))
+
+    def work(i):
+        d = pick[i]
+        st = oracle.pt_init(d["L"], d["live"], d["J"], d["K"], d["R"], d["instance_id"], seed)
+        oracle.pt_run(d["L"], d["live"], d["J"], d["K"], d["R"], d["beta"], d["instance_id"], seed,
+                      swap_interval, sweeps, st)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(cores)]
+    t0 = time.perf_counter()
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    el = time.perf_counter() - t0
+    live = sum(int(d["K"]) * int(d["R"]) * int(np.count_nonzero(d["live"])) for d in pick) * sweeps
+    return {"value": live / el, "unit": "spin-flip attempts/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} instances spread over the batch (one per thread) x {sweeps} sweeps, "
+                      f"{el:.1f} s wall"}
+
+
 def search_cpu_baseline(cfg, seeds, budget_s, sweeps_per_step, what="plain search step"):
     """The CPU oracle's hardness_eval, as it stands, on the host's cores: one
     seed instance per thread, two restarts each with the sweep cap lowered so
@@ -296,6 +332,8 @@ def uneven(args):
                      "ops_per_attempt": A_OPS},
         "energy_mismatches": mism,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = mixed_cpu_baseline(insts, cfg["seed"], cfg["swap_interval"], args.cpu_seconds)
     graph.close()
     batch.close()
     print(json.dumps(out), flush=True)
