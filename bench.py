@@ -525,13 +525,11 @@ def lao(args):
     from paper_1605_03607_amd import search as S
     cfg = S.SearchConfig(mode="plain", chains=args.search_chains)
     t0 = time.perf_counter()
-    run = S.LaoSearch(cfg, n_loops=350)
+    run = S.GroupedLao(cfg, n_loops=350, groups=args.search_groups)
     t_init = time.perf_counter() - t0
     sweeps0 = run.pt_sweeps
     t0 = time.perf_counter()
-    for k in range(args.search_steps):
-        run.run_step()
-        print(f"# lao: step {k + 1}/{args.search_steps}", file=sys.stderr, flush=True)
+    run.run(args.search_steps, progress=_search_progress("lao", args))
     wall = time.perf_counter() - t0
     tts0, tts = np.exp(run.ln0), np.exp(run.ln)
     ratio = tts / float(np.mean(tts0))
@@ -545,7 +543,7 @@ def lao(args):
         "dtype": "int32 (PT)", "data": "synthetic",
         "config": {"workload": f"LAO, {args.search_chains} planted C8 chains, 350 loops (weights 1..5, "
                                "P(4-cycle) 0.1), 32 restarts K32 R2, T_s 0.5",
-                   "bounded_steps": args.search_steps},
+                   "bounded_steps": args.search_steps, "chain_groups": args.search_groups},
         "ratio_median": float(np.median(ratio)), "ratio_max": float(np.max(ratio)),
         "initial_mean_ln_tts": float(np.mean(run.ln0)), "final_mean_ln_tts": float(np.mean(run.ln)),
         "accepted": run.accepted, "scored": run.scored, "pt_ground_state_equals_planted": run.gs_found,

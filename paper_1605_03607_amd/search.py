@@ -400,7 +400,7 @@ class LaoSearch:
     replacement loop under the coupling cap (kept as rejected moves), and
     `decisions` logs (step, chain, ln_cur, ln_new, w, accepted)."""
 
-    def __init__(self, cfg, n_loops, seed_chain0=0):
+    def __init__(self, cfg, n_loops, seed_chain0=0, score=True):
         from . import lao_init
         self.cfg = cfg
         self.n_loops = n_loops
@@ -417,6 +417,11 @@ class LaoSearch:
         self.accepted = 0
         self.voids = 0
         self.decisions = []
+        self.ln = self.ln0 = None
+        if score:
+            self.score_initial()
+
+    def score_initial(self):
         self.ln = self._score([(ch, i["J"], i["e_gs"]) for ch, i in enumerate(self.inst)])
         self.ln0 = self.ln.copy()
 
@@ -447,7 +452,8 @@ class LaoSearch:
                 self.voids += 1
                 continue
             ok = rao_accept(self.ln[ch], ln[ch], c.t_s, w)
-            self.decisions.append((self.step, ch, float(self.ln[ch]), float(ln[ch]), int(w), bool(ok)))
+            self.decisions.append((self.step, self.chain_id[ch], float(self.ln[ch]), float(ln[ch]), int(w),
+                                   bool(ok)))
             if ok:
                 inst = self.inst[ch]
                 inst["loops"] = inst["loops"].copy()
@@ -457,3 +463,54 @@ class LaoSearch:
                 self.ln[ch] = ln[ch]
                 self.accepted += 1
         self.step += 1
+
+
+class GroupedLao:
+    """LaoSearch's chains in `groups` contiguous groups stepping concurrently
+    on their own streams, as GroupedSearch does for Algorithm 1.  Chains
+    keep their global indices (planted instances, moves and PT streams are
+    keyed by them), so every decision is the one-group search's."""
+
+    def __init__(self, cfg, n_loops, groups=4):
+        import copy
+        n = cfg.chains
+        if not 1 <= groups <= n:
+            raise ValueError("need 1 <= groups <= chains")
+        self.cfg = cfg
+        cuts = [round(g * n / groups) for g in range(groups + 1)]
+        self.groups = []
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            cg = copy.copy(cfg)
+            cg.chains = b - a
+            self.groups.append(LaoSearch(cg, n_loops, seed_chain0=a, score=False))
+        _in_groups(groups, lambda i, failed: self.groups[i].score_initial())
+        self.init_pt_seconds = max(g.pt_seconds for g in self.groups)
+
+    def run(self, steps, progress=None):
+        def walk(i, failed):
+            g = self.groups[i]
+            for _ in range(steps):
+                if failed.is_set():
+                    return
+                g.run_step()
+                if progress is not None:
+                    progress(i, g.step)
+
+        _in_groups(len(self.groups), walk)
+
+    def _sum(self, name):
+        return sum(getattr(g, name) for g in self.groups)
+
+    ln = property(lambda self: np.concatenate([g.ln for g in self.groups]))
+    ln0 = property(lambda self: np.concatenate([g.ln0 for g in self.groups]))
+    inst = property(lambda self: [i for g in self.groups for i in g.inst])
+    decisions = property(lambda self: sorted(d for g in self.groups for d in g.decisions))
+    accepted = property(lambda self: self._sum("accepted"))
+    scored = property(lambda self: self._sum("scored"))
+    gs_found = property(lambda self: self._sum("gs_found"))
+    voids = property(lambda self: self._sum("voids"))
+    pt_seconds = property(lambda self: self._sum("pt_seconds"))
+    pt_sweeps = property(lambda self: self._sum("pt_sweeps"))
+    pt_device_ms = property(lambda self: self._sum("pt_device_ms"))
+    pt_attempts = property(lambda self: self._sum("pt_attempts"))
+    pt_calls = property(lambda self: self._sum("pt_calls"))

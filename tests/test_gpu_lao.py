@@ -54,3 +54,19 @@ def test_lao_search_decisions_follow_the_rule():
         assert np.array_equal(J.astype(np.int8), i["J"]) and e == i["e_gs"]
     assert run.scored == 4 + len(run.decisions) and run.voids == 12 - len(run.decisions)
     assert run.gs_found == run.scored
+
+
+def test_grouped_lao_takes_the_same_decisions():
+    hs = _gpu()
+    from paper_1605_03607_amd import search as S
+    cfg = S.SearchConfig(mode="plain", chains=5, L=2, restarts=4, K=8, R=2, s_max=3000)
+    one = S.LaoSearch(cfg, n_loops=14)
+    for _ in range(3):
+        one.run_step()
+    many = S.GroupedLao(cfg, n_loops=14, groups=2)
+    many.run(3)
+    assert many.decisions == sorted(one.decisions)
+    assert np.array_equal(many.ln0, one.ln0) and np.array_equal(many.ln, one.ln)
+    assert all(np.array_equal(a["J"], b["J"]) for a, b in zip(many.inst, one.inst))
+    assert (many.scored, many.voids, many.accepted, many.gs_found) == (one.scored, one.voids, one.accepted,
+                                                                        one.gs_found)

@@ -93,3 +93,18 @@ def test_group_count_is_checked(S):
     seeds = [workloads.couplings(2, "pm1", 53, c) for c in range(2)]
     with pytest.raises(ValueError):
         S.GroupedSearch(cfg, seeds, groups=3)
+
+
+def test_grouped_lao_takes_the_single_group_decisions(S):
+    cfg = S.SearchConfig(mode="plain", chains=5, L=2, t_s=0.7)
+    one = S.LaoSearch(cfg, n_loops=14)
+    for _ in range(4):
+        one.run_step()
+    many = S.GroupedLao(cfg, n_loops=14, groups=3)
+    seen = []
+    many.run(4, progress=lambda g, k: seen.append((g, k)))
+    assert sorted(seen) == [(g, k) for g in range(3) for k in range(1, 5)]
+    assert many.decisions == sorted(one.decisions)
+    assert np.array_equal(many.ln, one.ln) and np.array_equal(many.ln0, one.ln0)
+    assert all(np.array_equal(a["J"], b["J"]) for a, b in zip(many.inst, one.inst))
+    assert (many.scored, many.voids, many.accepted) == (one.scored, one.voids, one.accepted)
