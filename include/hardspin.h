@@ -32,6 +32,11 @@
  *   - Errors: every call returns HS_OK (0) or a negative HS_E* code and sets
  *     a thread-local message (hs_last_error).  Asynchronous device faults are
  *     reported as HS_EHIP by the next call that synchronises.
+ *   - Threads: calls on different handles and buffers may run concurrently
+ *     from different host threads (each on its own stream); one handle is
+ *     used by one thread at a time.  The library's shared state (the device's
+ *     compute-unit count, the planted-instance cycle lists) is initialised
+ *     once under a lock.
  */
 #ifndef HARDSPIN_H
 #define HARDSPIN_H
