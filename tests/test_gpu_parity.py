@@ -75,7 +75,7 @@ def test_c4_parity_config_full_length():
 def _uneven_instances():
     rng = np.random.default_rng(7)
     shapes = [(1, 2, 1), (1, 4, 16), (2, 8, 8), (3, 5, 3), (4, 64, 1), (5, 24, 2), (7, 31, 2),
-              (8, 32, 2), (9, 13, 4), (12, 48, 1), (6, 1, 64), (11, 2, 32)]
+              (8, 32, 2), (9, 13, 4), (12, 48, 1), (6, 1, 64), (11, 2, 32), (2, 1, 1)]
     insts = []
     for n, (L, K, R) in enumerate(shapes):
         alphabet = ["pm1", "pm3", "pm7"][n % 3]
