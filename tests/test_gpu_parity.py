@@ -199,6 +199,33 @@ def test_zero_sweeps_and_empty_batch():
     e.close()
 
 
+def test_free_spins_and_ferromagnet_match_oracle():
+    """Degenerate couplings: J = 0 (every attempt accepted, energy stays 0)
+    and the all-ferromagnetic instance (ground states all-up and all-down,
+    E = -|E|), bit-exact against the oracle, and hardness_eval finds the
+    closed-form ground energies."""
+    hs = _gpu()
+    L, K, R = 3, 8, 2
+    n_e = 24 * L * L - 8 * L
+    beta = workloads.geometric_betas(0.2, 4.0, K)
+    insts = [dict(L=L, J=np.zeros(n_e, np.int8), live=None, K=K, R=R, beta=beta, instance_id=51),
+             dict(L=L, J=np.full(n_e, -1, np.int8), live=None, K=K, R=R, beta=beta, instance_id=52)]
+    b = hs.PTBatch(insts, SEED, swap_interval=1)
+    b.sweep(300)
+    for n, d in enumerate(insts):
+        _say(f"degenerate couplings: instance {n}")
+        o = oracle.pt_init(L, None, d["J"], K, R, d["instance_id"], SEED)
+        oracle.pt_run(L, None, d["J"], K, R, beta, d["instance_id"], SEED, 1, 300, o)
+        _assert_same(b.state(n), o, f"instance {n}")
+    assert np.all(b.state(0)["energy"][:K * R] == 0)
+    assert b.measure() == 0
+    b.close()
+    cands = [dict(L=L, J=d["J"], live=None, instance_id=d["instance_id"]) for d in insts]
+    ln, det = hs.hardness_eval(cands, 4, K, R, beta, 1, 5000, 77)
+    assert det[0]["e_gs"] == 0 and det[1]["e_gs"] == -n_e
+    assert all(np.isfinite(ln))
+
+
 def test_hardness_eval_matches_oracle():
     hs = _gpu()
     beta = workloads.geometric_betas(0.1, 5.0, 8)
