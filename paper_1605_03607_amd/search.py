@@ -43,7 +43,7 @@ import time
 
 import numpy as np
 
-from . import Surrogate, gnn_fan_ins, hardness_eval, instance_mutate, rao_accept
+from . import Surrogate, hardness_eval, instance_mutate, rao_accept
 
 ALPHABET_PM7 = np.array([-7, -6, -5, -4, -3, -2, -1, 1, 2, 3, 4, 5, 6, 7], np.int8)
 ALPHABET_PM1 = np.array([-1, 1], np.int8)  # Algorithm 1's sign flips
@@ -64,6 +64,8 @@ def _timed_hardness(cands, c):
 
 
 def _geometric(lo, hi, k):
+    if k == 1:
+        return np.array([float(lo)])
     return lo * (hi / lo) ** (np.arange(k) / (k - 1))
 
 
