@@ -516,3 +516,107 @@ class GroupedLao:
     pt_device_ms = property(lambda self: self._sum("pt_device_ms"))
     pt_attempts = property(lambda self: self._sum("pt_attempts"))
     pt_calls = property(lambda self: self._sum("pt_calls"))
+
+
+# ---------------------------------------------------------------------------
+# Checkpoint and resume.  A search is saved between whole steps: the chains'
+# couplings, ln TTS, the step, the counted states, the decision log and the
+# shared pool (replay buffer, training draws, surrogate weights and Adam
+# state).  Every other draw is keyed by (seed, step, chain), so nothing else
+# is needed to continue exactly.  The file is a numpy archive without pickled
+# objects, written to a temporary name and renamed, so a process killed while
+# saving leaves the previous checkpoint intact.
+
+_CKPT_VERSION = 1
+_CFG_KEYS = ("mode", "direction", "chains", "L", "restarts", "K", "R", "swap_interval", "s_max", "t_s", "seed",
+             "proposals", "top", "train_steps", "train_batch", "lr", "replay")
+
+
+def _cfg_record(cfg):
+    rec = {k: getattr(cfg, k) for k in _CFG_KEYS}
+    rec["beta"] = [float(b) for b in cfg.beta]
+    rec["alphabet"] = [int(a) for a in cfg.alphabet]
+    return rec
+
+
+def save_search(run, path):
+    """Checkpoint of a Search or GroupedSearch (all groups at the same step)."""
+    import json
+    import os
+    groups = run.groups if isinstance(run, GroupedSearch) else [run]
+    steps = {g.step for g in groups}
+    if len(steps) != 1:
+        raise ValueError("groups are at different steps")
+    pool = groups[0].pool
+    cfg = groups[0].cfg
+    hard = {}
+    for g in groups:
+        for b, keys in g.hard.items():
+            hard.setdefault(repr(float(b)), set()).update(keys)
+    dec = sorted(d for g in groups for d in g.decisions)
+    meta = {"version": _CKPT_VERSION, "cfg": _cfg_record(cfg), "step": steps.pop(),
+            "h0": groups[0].h0, "accepted": sum(g.accepted for g in groups),
+            "hard": {b: sorted(k) for b, k in hard.items()},
+            "rng": pool.rng.bit_generator.state, "sur_step": pool.sur.step if pool.sur is not None else 0}
+    arrays = {
+        "meta": np.frombuffer(json.dumps(meta).encode(), np.uint8),
+        "ids": np.array([i for g in groups for i in g.ids], np.int64),
+        "J": np.stack([J for g in groups for J in g.J]).astype(np.int8),
+        "ln": np.concatenate([g.ln for g in groups]).astype(np.float64),
+        "decisions": np.array([[d[0], d[1], d[2], d[3], d[4], float(d[5])] for d in dec], np.float64).reshape(-1, 6),
+        "pairs_J": (np.stack(pool.pairs_J).astype(np.int8) if pool.pairs_J
+                    else np.zeros((0, len(groups[0].J[0])), np.int8)),
+        "pairs_y": np.array(pool.pairs_y, np.float64),
+    }
+    if pool.sur is not None:
+        arrays["sur_params"] = pool.sur.params.cpu().numpy()
+        arrays["sur_m"] = pool.sur.m.cpu().numpy()
+        arrays["sur_v"] = pool.sur.v.cpu().numpy()
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **arrays)
+    os.replace(tmp, path)
+
+
+def load_search(path, cfg, groups=1):
+    """Resume a checkpoint as a Search (groups = 1) or a GroupedSearch.  cfg
+    must equal the saved configuration; the grouping may differ, since no
+    decision depends on it."""
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        a = {k: z[k] for k in z.files}
+    meta = json.loads(a["meta"].tobytes().decode())
+    if meta["version"] != _CKPT_VERSION:
+        raise ValueError("unknown checkpoint version")
+    if meta["cfg"] != json.loads(json.dumps(_cfg_record(cfg))):
+        raise ValueError("checkpoint was written with another search configuration")
+    n = len(a["ids"])
+    if not 1 <= groups <= n:
+        raise ValueError("need 1 <= groups <= chains")
+    pool = _Pool(cfg, a["sur_params"] if "sur_params" in a else None)
+    pool.pairs_J = [row.copy() for row in a["pairs_J"]]
+    pool.pairs_y = [float(y) for y in a["pairs_y"]]
+    pool.rng.bit_generator.state = meta["rng"]
+    if pool.sur is not None:
+        torch = pool.sur.torch
+        pool.sur.m.copy_(torch.from_numpy(a["sur_m"]))
+        pool.sur.v.copy_(torch.from_numpy(a["sur_v"]))
+        pool.sur.step = int(meta["sur_step"])
+    cuts = [round(g * n / groups) for g in range(groups + 1)]
+    parts = []
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        g = Search(cfg, [a["J"][i] for i in range(lo, hi)], chain_ids=a["ids"][lo:hi].tolist(), pool=pool,
+                   ln=a["ln"][lo:hi], h0=meta["h0"])
+        g.step = int(meta["step"])
+        parts.append(g)
+    owner = {int(i): g for g in parts for i in g.ids}
+    for row in a["decisions"]:
+        d = (int(row[0]), int(row[1]), float(row[2]), float(row[3]), int(row[4]), bool(row[5]))
+        owner[d[1]].decisions.append(d)
+    parts[0].accepted = int(meta["accepted"])
+    parts[0].hard = {float(b): set(keys) for b, keys in meta["hard"].items()}
+    if groups == 1:
+        return parts[0]
+    run = GroupedSearch.__new__(GroupedSearch)
+    run.cfg, run.pool, run.groups, run.h0 = cfg, pool, parts, float(meta["h0"])
+    run.init_pt_seconds, run.init_pt_sweeps = 0.0, 0
+    return run

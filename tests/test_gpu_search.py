@@ -97,3 +97,33 @@ def test_grouped_surrogate_search_runs():
     assert all(many.ln[ch] == cur[ch] for ch in range(chains))
     assert many.pool.sur.step == 3 * sum(g.train_steps for g in many.groups)
     assert np.isfinite(many.pool.sur.params.cpu().numpy()).all()
+
+
+def test_surrogate_search_checkpoint_restores_the_network(tmp_path):
+    """Weights, Adam moments and step, replay buffer and training draws come
+    back exactly: the restored network's predictions equal the original's,
+    and the restored search continues."""
+    hs = _gpu()
+    from paper_1605_03607_amd import search as S
+    chains = 4
+    cfg = S.SearchConfig(mode="surrogate", chains=chains, L=2, restarts=4, K=8, R=2, s_max=3000, proposals=6,
+                         top=2, train_steps=2, train_batch=4)
+    seeds = [workloads.couplings(2, "pm1", 43, c) for c in range(chains)]
+    params = workloads.gnn_params(hs.lib().gnn_param_count(), hs.gnn_fan_ins())
+    run = S.Search(cfg, seeds, surrogate_params=params)
+    for _ in range(2):
+        run.run_step(bars=(math.log(1.5),))
+    path = str(tmp_path / "sur.npz")
+    S.save_search(run, path)
+    back = S.load_search(path, cfg)
+    a, b = run.pool, back.pool
+    for name in ("params", "m", "v"):
+        assert np.array_equal(getattr(a.sur, name).cpu().numpy(), getattr(b.sur, name).cpu().numpy()), name
+    assert a.sur.step == b.sur.step
+    assert a.pairs_y == b.pairs_y and all(np.array_equal(x, y) for x, y in zip(a.pairs_J, b.pairs_J))
+    assert a.rng.bit_generator.state == b.rng.bit_generator.state
+    graphs = [(2, None, J) for J in run.J]
+    assert np.array_equal(a.sur.forward(graphs), b.sur.forward(graphs))
+    assert back.step == 2 and back.decisions == run.decisions and np.array_equal(back.ln, run.ln)
+    back.run_step(bars=(math.log(1.5),))
+    assert len(back.decisions) == 3 * chains

@@ -108,3 +108,95 @@ def test_grouped_lao_takes_the_single_group_decisions(S):
     assert np.array_equal(many.ln, one.ln) and np.array_equal(many.ln0, one.ln0)
     assert all(np.array_equal(a["J"], b["J"]) for a, b in zip(many.inst, one.inst))
     assert (many.scored, many.voids, many.accepted) == (one.scored, one.voids, one.accepted)
+
+
+@pytest.mark.parametrize("mode,groups_before,groups_after", [("plain", 1, 1), ("random", 3, 2), ("plain", 2, 1)])
+def test_checkpoint_resume_is_exact(S, tmp_path, mode, groups_before, groups_after):
+    chains, steps = 6, 4
+    cfg = S.SearchConfig(mode=mode, chains=chains, L=2, proposals=5, top=2, t_s=0.7)
+    seeds = [workloads.couplings(2, "pm1", 61, c) for c in range(chains)]
+    bars = (math.log(1.2),)
+    full = S.Search(cfg, seeds)
+    for _ in range(steps):
+        full.run_step(bars)
+    run = S.GroupedSearch(cfg, seeds, groups=groups_before) if groups_before > 1 else S.Search(cfg, seeds)
+    if groups_before > 1:
+        run.run(2, bars)
+    else:
+        run.run_step(bars)
+        run.run_step(bars)
+    path = str(tmp_path / "search.npz")
+    S.save_search(run, path)
+    back = S.load_search(path, cfg, groups=groups_after)
+    if groups_after > 1:
+        back.run(steps - 2, bars)
+    else:
+        for _ in range(steps - 2):
+            back.run_step(bars)
+    assert sorted(back.decisions) == sorted(full.decisions)
+    assert np.array_equal(back.ln, full.ln)
+    assert all(np.array_equal(a, b) for a, b in zip(back.J, full.J))
+    assert back.hard == full.hard and back.accepted == full.accepted
+    if groups_before == groups_after == 1:
+        assert back.pool.pairs_y == full.pool.pairs_y
+        assert all(np.array_equal(a, b) for a, b in zip(back.pool.pairs_J, full.pool.pairs_J))
+    else:  # concurrent groups add their pairs in the order they finish
+        assert sorted(back.pool.pairs_y) == sorted(full.pool.pairs_y)
+
+
+def test_checkpoint_rejects_another_configuration(S, tmp_path):
+    cfg = S.SearchConfig(mode="plain", chains=3, L=2)
+    seeds = [workloads.couplings(2, "pm1", 67, c) for c in range(3)]
+    run = S.Search(cfg, seeds)
+    run.run_step()
+    path = str(tmp_path / "c.npz")
+    S.save_search(run, path)
+    other = S.SearchConfig(mode="plain", chains=3, L=2, t_s=0.9)
+    with pytest.raises(ValueError, match="configuration"):
+        S.load_search(path, other)
+
+
+_CHILD = r"""
+import math, os, signal, sys
+sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
+import numpy as np
+import workloads
+import paper_1605_03607_amd as hs
+hs.lib()
+from paper_1605_03607_amd import search as S
+import test_search_groups as T
+S.hardness_eval = T._fake_eval
+def untimed(cands, c):
+    ln, det = S.hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
+    return ln, det, 0.0, 0
+S._timed_hardness = untimed
+cfg = S.SearchConfig(mode="random", chains=5, L=2, proposals=5, top=2, t_s=0.7)
+run = S.Search(cfg, [workloads.couplings(2, "pm1", 71, c) for c in range(5)])
+for k in range(3):
+    run.run_step((math.log(1.2),))
+    S.save_search(run, {path!r})
+os.kill(os.getpid(), signal.SIGKILL)  # dies without any cleanup
+"""
+
+
+def test_resume_after_a_killed_process(S, tmp_path):
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = str(tmp_path / "killed.npz")
+    code = _CHILD.format(root=root, tests=os.path.join(root, "tests"), path=path)
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, timeout=300)
+    assert p.returncode == -9, p.stderr.decode()[-2000:]
+    cfg = S.SearchConfig(mode="random", chains=5, L=2, proposals=5, top=2, t_s=0.7)
+    seeds = [workloads.couplings(2, "pm1", 71, c) for c in range(5)]
+    full = S.Search(cfg, seeds)
+    for _ in range(5):
+        full.run_step((math.log(1.2),))
+    back = S.load_search(path, cfg)
+    assert back.step == 3
+    back.run_step((math.log(1.2),))
+    back.run_step((math.log(1.2),))
+    assert back.decisions == full.decisions
+    assert np.array_equal(back.ln, full.ln)
+    assert back.hard == full.hard
