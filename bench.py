@@ -89,6 +89,8 @@ def parse():
     p.add_argument("--search-chains", type=int, default=64)
     p.add_argument("--search-groups", type=int, default=4,
                    help="chain groups stepping concurrently on their own streams (search workloads)")
+    p.add_argument("--search-log", default=None,
+                   help="search workloads: write every acceptance decision as a JSON line to this file")
     p.add_argument("--tau-emcs", type=int, default=20000, help="EMCS of the --workload tau run")
     p.add_argument("--probe", action="store_true",
                    help="also measure instruction issue rates (libhsprobe.so)")
@@ -341,6 +343,16 @@ def uneven(args):
     print(json.dumps(out), flush=True)
 
 
+def _write_decisions(args, arm, run, mode="a"):
+    """One JSON line per acceptance decision of a search arm."""
+    if not args.search_log:
+        return
+    with open(args.search_log, mode) as f:
+        for step, chain, ln_cur, ln_new, w, ok in run.decisions:
+            f.write(json.dumps({"arm": arm, "step": step, "chain": chain, "ln_tts_current": ln_cur,
+                                "ln_tts_candidate": ln_new, "w": w, "accepted": ok}) + "\n")
+
+
 def _search_progress(name, args):
     def report(group, step):
         print(f"# {name}: group {group + 1}/{args.search_groups} step {step}/{args.search_steps}",
@@ -371,6 +383,7 @@ def search(args):
         wall = time.perf_counter() - t0
         hours = wall / 3600.0
         hard = {name: len(run.hard.get(b, set())) for name, b in bars.items()}
+        _write_decisions(args, mode, run, "w" if mode == "plain" else "a")
         finite = np.isfinite(run.ln)
         arms[mode] = {
             "steps": args.search_steps, "seconds": wall, "s_per_step": wall / args.search_steps,
@@ -427,6 +440,7 @@ def search_reverse(args):
     run.run(args.search_steps, bars=tuple(bars.values()), progress=_search_progress("reverse", args))
     wall = time.perf_counter() - t0
     easy = {name: len(run.hard.get(b, set())) for name, b in bars.items()}
+    _write_decisions(args, "reverse", run, "w")
     med = float(np.median(run.ln))
     out = {
         "metric": "easy instances/hour (reversed search)",
@@ -534,6 +548,7 @@ def lao(args):
     run.run(args.search_steps, progress=_search_progress("lao", args))
     wall = time.perf_counter() - t0
     tts0, tts = np.exp(run.ln0), np.exp(run.ln)
+    _write_decisions(args, "lao", run, "w")
     ratio = tts / float(np.mean(tts0))
     out = {
         "metric": "LAO: final TTS / mean initial TTS (planted C8)",
