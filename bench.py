@@ -89,6 +89,8 @@ def parse():
     p.add_argument("--search-chains", type=int, default=64)
     p.add_argument("--search-groups", type=int, default=4,
                    help="chain groups stepping concurrently on their own streams (search workloads)")
+    p.add_argument("--search-top", type=int, default=2,
+                   help="screened arms: proposals per chain scored by PT after the screen")
     p.add_argument("--search-log", default=None,
                    help="search workloads: write every acceptance decision as a JSON line to this file")
     p.add_argument("--tau-emcs", type=int, default=20000, help="EMCS of the --workload tau run")
@@ -372,7 +374,7 @@ def search(args):
     bars = {"ln3": math.log(3.0), "ln10": math.log(10.0), "ln30": math.log(30.0)}
     arms = {}
     for mode in ("plain", "surrogate", "random"):
-        cfg = S.SearchConfig(mode=mode, chains=args.search_chains)
+        cfg = S.SearchConfig(mode=mode, chains=args.search_chains, top=args.search_top)
         params = workloads.gnn_params(hs.lib().gnn_param_count(), hs.gnn_fan_ins())
         t0 = time.perf_counter()
         run = S.GroupedSearch(cfg, seeds, groups=args.search_groups,
@@ -406,7 +408,8 @@ def search(args):
         "dtype": "int32 (PT) / bf16-fp32 (surrogate)", "data": "synthetic",
         "config": {"workload": f"instance search, {args.search_chains} C8 chains, +-1 seeds, "
                                "mutations in +-1..+-7, 32 restarts K32 R2, T_s 0.5",
-                   "bounded_steps": args.search_steps, "chain_groups": args.search_groups},
+                   "bounded_steps": args.search_steps, "chain_groups": args.search_groups,
+                   "screen": f"16 proposals, top {args.search_top} scored by PT"},
         "surrogate_over_plain": (rate("surrogate") / rate("plain")) if rate("plain") > 0 else None,
         "arms": arms,
         "roofline": pt_roofline(sum(a["pt_attempts"] for a in arms.values()),
