@@ -267,6 +267,30 @@ def test_full_size_c8_batch_sampled(swap_interval):
     b.close()
 
 
+def test_full_size_c8_batch_every_instance_prefix():
+    """All 256 instances of the benchmark batch after a 10^3-sweep prefix of
+    the benchmark launch (one persistent launch, exchange every sweep),
+    each re-run on the oracle in a pool of host threads: bit-exact."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    hs = _gpu()
+    cfg = workloads.batch_c8()
+    insts = workloads.make_batch(cfg)
+    n_sweeps = 1000
+    b = hs.PTBatch(insts, cfg["seed"], swap_interval=1)
+    b.sweep(n_sweeps)
+    assert b.measure() == 0
+    got = [b.state(n) for n in range(len(insts))]
+    b.close()
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(workers) as pool:
+        futs = [pool.submit(_oracle_run, d, cfg["seed"], 1, n_sweeps) for d in insts]
+        for n, f in enumerate(futs):
+            if n % 32 == 0:
+                _say(f"C8 every-instance prefix: instance {n} of {len(insts)}")
+            _assert_same(got[n], f.result(), f"instance {n}")
+
+
 @pytest.mark.parametrize("K,R", [(32, 2), (64, 1), (1, 64), (2, 32)])
 def test_largest_lattice_parity(K, R):
     """C16 (the largest lattice the engine takes, N = 2048) with 2% missing
