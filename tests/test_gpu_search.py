@@ -127,3 +127,41 @@ def test_surrogate_search_checkpoint_restores_the_network(tmp_path):
     assert back.step == 2 and back.decisions == run.decisions and np.array_equal(back.ln, run.ln)
     back.run_step(bars=(math.log(1.5),))
     assert len(back.decisions) == 3 * chains
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+def test_plain_search_replays_on_the_oracle(direction):
+    """Algorithm 1 end to end on C4: the oracle replays every step (its own
+    mutation, its own PT hardness of the candidate, its own acceptance) and
+    reaches the same ln TTS, decisions and couplings as the GPU search."""
+    hs = _gpu()
+    from paper_1605_03607_amd import search as S
+    chains, steps, L = 3, 5, 4
+    cfg = S.SearchConfig(mode="plain", chains=chains, L=L, restarts=4, K=8, R=2, s_max=3000, direction=direction,
+                         alphabet=S.ALPHABET_PM1 if direction < 0 else S.ALPHABET_PM7)
+    seeds = [workloads.couplings(L, "pm1", 83, c) for c in range(chains)]
+    run = S.Search(cfg, seeds)
+    start = run.ln.copy()
+    for _ in range(steps):
+        run.run_step(bars=(math.log(1.5),))
+
+    def hard(J, ch):
+        return oracle.hardness_eval(L, None, J, ch, cfg.seed, cfg.restarts, cfg.K, cfg.R, cfg.beta,
+                                    cfg.swap_interval, cfg.s_max)["ln_tts"]
+    want = []
+    for ch in range(chains):
+        print(f"search replay on the oracle: chain {ch}", flush=True)
+        J = np.array(seeds[ch], np.int8)
+        ln = hard(J, ch)
+        assert ln == start[ch]
+        for k in range(steps):
+            e, old, new, w = oracle.mutate(L, None, J, cfg.alphabet, ch, cfg.seed, k, 0)
+            J2 = J.copy()
+            J2[e] = new
+            ln2 = hard(J2, ch)
+            ok = oracle.rao_accept(direction * ln, direction * ln2, cfg.t_s, w)
+            want.append((k, ch, ln, ln2, w, ok))
+            if ok:
+                J, ln = J2, ln2
+        assert np.array_equal(run.J[ch], J) and run.ln[ch] == ln
+    assert sorted(want) == sorted(run.decisions)
