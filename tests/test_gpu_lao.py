@@ -70,3 +70,45 @@ def test_grouped_lao_takes_the_same_decisions():
     assert all(np.array_equal(a["J"], b["J"]) for a, b in zip(many.inst, one.inst))
     assert (many.scored, many.voids, many.accepted, many.gs_found) == (one.scored, one.voids, one.accepted,
                                                                         one.gs_found)
+
+
+def test_lao_search_replays_on_the_oracle():
+    """Algorithm 2 end to end on C3: the oracle's planted instances, loop
+    moves, PT hardness and acceptance reproduce the GPU search's ln TTS,
+    decisions, loops and planted energies over 4 steps."""
+    hs = _gpu()
+    from paper_1605_03607_amd import search as S
+    L, chains, steps, n_loops = 3, 3, 4, 30
+    cfg = S.SearchConfig(mode="plain", chains=chains, L=L, restarts=4, K=8, R=2, s_max=3000)
+    run = S.LaoSearch(cfg, n_loops=n_loops)
+    for _ in range(steps):
+        run.run_step()
+    cyc = P.cycles(L)
+
+    def hard(J, ch):
+        return oracle.hardness_eval(L, None, J, ch, cfg.seed, cfg.restarts, cfg.K, cfg.R, cfg.beta,
+                                    cfg.swap_interval, cfg.s_max)
+    want = []
+    for ch in range(chains):
+        print(f"LAO replay on the oracle: chain {ch}", flush=True)
+        inst = P.init(L, n_loops, ch, cfg.seed, cyc=cyc)
+        h = hard(inst["J"], ch)
+        assert h["e_gs"] == inst["e_gs"] and h["ln_tts"] == run.ln0[ch]
+        ln = h["ln_tts"]
+        for k in range(steps):
+            slot, lp, w, J2, e2 = P.move(L, inst, ch, cfg.seed, k, 0, cyc=cyc)
+            if slot < 0:
+                continue
+            h2 = hard(J2, ch)
+            assert h2["e_gs"] == e2
+            ok = oracle.rao_accept(ln, h2["ln_tts"], cfg.t_s, w)
+            want.append((k, ch, ln, h2["ln_tts"], w, ok))
+            if ok:
+                loops = list(inst["loops"])
+                loops[slot] = lp
+                inst = dict(loops=loops, bits=inst["bits"], J=J2, e_gs=e2)
+                ln = h2["ln_tts"]
+        assert np.array_equal(run.inst[ch]["J"], inst["J"]) and run.inst[ch]["e_gs"] == inst["e_gs"]
+        assert [tuple(r) for r in run.inst[ch]["loops"].tolist()] == [tuple(x) for x in inst["loops"]]
+        assert run.ln[ch] == ln
+    assert sorted(want) == sorted(run.decisions)
