@@ -2,7 +2,7 @@
  * hs_gnn -- C ABI of the hardness surrogate: a small edge message-passing
  * network that ranks proposed coupler mutations of the instance search
  * (Algorithm 1, Sec. II.A, proposes one mutation per step; the surrogate
- * screens several and parallel tempering judges the survivors).  The network
+ * screens several and parallel tempering scores the survivors).  The network
  * has no counterpart in the paper; its definition is:
  *
  *   graph of an instance on Chimera C_L (Appendix A, Fig. 8):

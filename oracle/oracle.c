@@ -27,7 +27,7 @@
  *   - Brute-force enumeration of all 2^N configurations (definition of the
  *     ground state of Eq. 1; used only to pin the above).
  *
- * Readings where the paper is silent (each one is listed in the design doc):
+ * Readings where the paper is silent:
  *   spin bit b = 1 <-> s = -1; checkerboard sweep order (colour (r+c+u) mod 2,
  *   colour 0 first); Philox4x32-10 (Salmon et al., SC'11) with the counter
  *   layout below; a 32-bit uniform u = (hi16 << 16) | lo16 drawn from two

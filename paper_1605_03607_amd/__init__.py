@@ -3,8 +3,8 @@
 Every step of the parallel-tempering path runs in the library's gfx950
 kernels; this module only converts numpy / torch arguments into the C ABI of
 include/hardspin.h.  PyTorch is used for device memory and streams.  The
-library must have been built (`python -m paper_1605_03607_amd.build` or
-__graft_entry__.build()); importing the binding fails loudly otherwise.
+library must have been built (`python -m paper_1605_03607_amd.build`);
+importing the binding fails loudly otherwise.
 """
 import ctypes as C
 import os

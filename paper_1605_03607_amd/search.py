@@ -15,7 +15,7 @@ and accepts by Metropolis in ln TTS at search temperature t_s
   random     as surrogate, but the `top` candidates are chosen at random
              (the ablation: what ranking by the network gains)
 
-PT stays the judge of every accepted instance.  A hard instance is an
+PT scores every instance that can be accepted.  A hard instance is an
 accepted state with ln TTS >= H0 + ln(bar), H0 = median ln TTS of the seed
 instances; distinct hard instances are counted by their couplings.
 
