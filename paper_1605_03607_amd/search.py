@@ -297,7 +297,8 @@ def _in_groups(n, fn):
 class GroupedSearch:
     """The chains of one search in `groups` contiguous groups that step
     concurrently, each in a host thread with a stream of its own (default
-    priority).  Each group scores its own seeds, concurrently; H0 is the
+    priority).  Groups beyond the process's hardware queues (4 by default)
+    share a queue, and a launch then waits behind another's tail.  Each group scores its own seeds, concurrently; H0 is the
     median over all chains and the seeds enter the replay buffer in chain
     order, as in Search.  The attributes mirror Search's, merged over the
     groups; pt_seconds sums the groups' (overlapping) PT calls."""
