@@ -31,10 +31,12 @@ def _instances():
     return out
 
 
-def test_recorded_walk_matches_oracle_and_sweeps_are_unchanged():
+@pytest.mark.parametrize("si,n_emcs,cap", [(10, 60, 50), (1, 200, 256), (3, 40, 40)])
+def test_recorded_walk_matches_oracle_and_sweeps_are_unchanged(si, n_emcs, cap):
+    """Exchange every sweep, every 3rd and every 10th; a buffer shorter than
+    the run (later passes are not written), longer, and exactly full."""
     hs, torch = _gpu()
     insts = _instances()
-    si, n_emcs, cap = 10, 60, 50
     b = hs.PTBatch(insts, SEED, swap_interval=si)
     walk = torch.full((len(insts), cap, 64), 0xEE, dtype=torch.uint8, device="cuda")
     b.sweep_record(si * n_emcs, walk)
@@ -44,8 +46,10 @@ def test_recorded_walk_matches_oracle_and_sweeps_are_unchanged():
     for n, d in enumerate(insts):
         C = d["K"] * d["R"]
         traj, st = W.walk(d["L"], d["live"], d["J"], d["K"], d["R"], d["beta"], d["instance_id"], SEED, si, n_emcs)
-        assert np.array_equal(got[n, :, :C], traj[:cap]), f"instance {n}"
+        rec = min(cap, n_emcs)
+        assert np.array_equal(got[n, :rec, :C], traj[:rec]), f"instance {n}"
         assert np.all(got[n, :, C:] == 0xEE)  # beyond K R: untouched
+        assert np.all(got[n, rec:] == 0xEE)  # beyond the run: untouched
         a, r = b.state(n), ref.state(n)
         for name in ("spins", "perm", "energy", "emin", "thit", "swap_acc"):
             assert np.array_equal(a[name], r[name]), name
