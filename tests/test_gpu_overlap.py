@@ -78,7 +78,8 @@ def test_full_buffer_counts_but_stops_writing():
     assert set(meta[:, 0].tolist()) <= {0, 1}
 
 
-@pytest.mark.parametrize("L,n,n_levels,frac_missing", [(3, 300, 3, 0.0), (4, 257, 2, 0.05), (2, 40, 1, 0.0)])
+@pytest.mark.parametrize("L,n,n_levels,frac_missing", [(3, 300, 3, 0.0), (4, 257, 2, 0.05), (2, 40, 1, 0.0),
+                                                      (2, 1, 1, 0.0), (3, 2, 2, 0.0)])
 def test_overlap_summary_of_many_states_matches_oracle(L, n, n_levels, frac_missing):
     """Many distinct states, repeats and global flips on up to three levels
     (the medians run over thousands of pairs with many equal overlaps)."""
