@@ -343,12 +343,12 @@ __global__ void k_readout_bwd(const float *dy, const float *P, const float *live
 // dZ = dY * (Z > 0) as bfloat16, and the bias gradient (float).  For edges
 // dY = dM (from the layer above, column 128.. of its input gradient; none
 // for the top layer) + dS of the edge's destination (column 64.. of the node
-// input gradient).  Each workgroup adds its 64 bias sums atomically, so the
-// grid is capped: every workgroup adds to the same 64 addresses, and 2048
-// workgroups spent most of the kernel queued on them.
-constexpr unsigned kReluBlocks = 384;
+// input gradient).  Each workgroup stores its 64 partial bias sums in
+// bpart[blockIdx.x][64]; k_bias_sum adds them up (no atomics on the 64 shared
+// addresses, and the same sum on every run).
+constexpr unsigned kReluBlocks = 2048;
 __global__ void __launch_bounds__(256) k_relu_bwd(int rows, const float *dY, int ldY, int offY, const float *dS,
-                                                  const int32_t *dst, const float *Z, uint16_t *dZb, float *gb)
+                                                  const int32_t *dst, const float *Z, uint16_t *dZb, float *bpart)
 {
     __shared__ float part[4][D];
     const int t = threadIdx.x, d = t & 63, q = t >> 6;
@@ -362,7 +362,24 @@ __global__ void __launch_bounds__(256) k_relu_bwd(int rows, const float *dY, int
     }
     part[q][d] = s;
     __syncthreads();
-    if (t < D) atomicAdd(&gb[d], part[0][d] + part[1][d] + part[2][d] + part[3][d]);
+    if (t < D) bpart[int64_t(blockIdx.x) * D + d] = part[0][d] + part[1][d] + part[2][d] + part[3][d];
+}
+
+// gb[d] += sum over the nb rows of bpart[.][d]: one workgroup per column, a
+// fixed reduction tree.
+__global__ void __launch_bounds__(256) k_bias_sum(const float *bpart, int nb, float *gb)
+{
+    __shared__ float red[256];
+    const int d = blockIdx.x, t = threadIdx.x;
+    float s = 0.f;
+    for (int b = t; b < nb; b += 256) s += bpart[int64_t(b) * D + d];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) gb[d] += red[0];
 }
 
 // dH_v = dXn[v][0..63] + sum over out-edges e of dXe[e][0..63] + sum over
@@ -443,7 +460,7 @@ namespace {
 struct Layout {
     int G = 0, L = 0, N = 0, E = 0;
     int64_t nn = 0, nq = 0, ne = 0;
-    size_t xn, xe, live, nlive, src, dst, outE, wb, H, M, S, Zm, Zh, mean, y, dy, dZ, dXe, dXn, dH, total;
+    size_t xn, xe, live, nlive, src, dst, outE, wb, H, M, S, Zm, Zh, mean, y, dy, dZ, dXe, dXn, dH, bpart, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -484,6 +501,7 @@ bool make_layout(int G, int L, Layout &o)
     o.dXe = take(size_t(2) * o.ne * 192 * 4);
     o.dXn = take(size_t(o.nn) * 128 * 4);
     o.dH = take(size_t(o.nn) * D * 4);
+    o.bpart = take(size_t(kReluBlocks) * D * 4);
     o.total = p;
     return true;
 }
@@ -491,7 +509,7 @@ bool make_layout(int G, int L, Layout &o)
 int hip_err(hipError_t e, const char *what) { return fail(HS_EHIP, std::string(what) + ": " + hipGetErrorString(e)); }
 
 struct Bufs {
-    float *xn, *xe, *live, *nlive, *mean, *y, *dy, *dXe[2], *dXn, *dH, *Zm[kLayers], *Zh[kLayers];
+    float *xn, *xe, *live, *nlive, *mean, *y, *dy, *dXe[2], *dXn, *dH, *bpart, *Zm[kLayers], *Zh[kLayers];
     int32_t *src, *dst, *outE;
     uint16_t *H[kLayers + 1], *M[kLayers + 1], *S[kLayers], *dZ;
     WeightsBf wb;
@@ -536,6 +554,7 @@ Bufs views(const Layout &o, void *ws)
     v.dXe[1] = v.dXe[0] + size_t(o.ne) * 192;
     v.dXn = reinterpret_cast<float *>(b + o.dXn);
     v.dH = reinterpret_cast<float *>(b + o.dH);
+    v.bpart = reinterpret_cast<float *>(b + o.bpart);
     return v;
 }
 
@@ -695,8 +714,10 @@ int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labe
     for (int l = kLayers - 1; l >= 0; --l) {
         float *gl = grad + kLayer0 + l * kLayerSize;
         // node update
-        hipLaunchKernelGGL(k_relu_bwd, dim3(std::min<unsigned>(blocks_for(nn, 4), kReluBlocks)), dim3(256), 0, st, nn,
-                           v.dH, D, 0, nullptr, nullptr, v.Zh[l], v.dZ, gl + kBh);
+        const unsigned gn = std::min<unsigned>(blocks_for(nn, 4), kReluBlocks);
+        hipLaunchKernelGGL(k_relu_bwd, dim3(gn), dim3(256), 0, st, nn, v.dH, D, 0, nullptr, nullptr, v.Zh[l], v.dZ,
+                           v.bpart);
+        hipLaunchKernelGGL(k_bias_sum, dim3(D), dim3(256), 0, st, v.bpart, int(gn), gl + kBh);
         Seg xn{{v.H[l], v.S[l], nullptr}, {nullptr, nullptr, nullptr}};
         hipLaunchKernelGGL(k_wgrad<2>, dim3(blocks_for(nn, kRowsPerBlock)), dim3(256), 0, st, nn, v.dZ, xn,
                            gl + kWh);
@@ -704,8 +725,10 @@ int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labe
         hipLaunchKernelGGL((k_rows<1, 8>), dim3(blocks_for(nn, 64)), dim3(256), 0, st, nn, dzn, v.wb.whT[l],
                            nullptr, v.dXn, nullptr);
         // edge update
-        hipLaunchKernelGGL(k_relu_bwd, dim3(std::min<unsigned>(blocks_for(ne, 4), kReluBlocks)), dim3(256), 0, st, ne,
-                           dXe_above, 192, 128, v.dXn, v.dst, v.Zm[l], v.dZ, gl + kBm);
+        const unsigned ge = std::min<unsigned>(blocks_for(ne, 4), kReluBlocks);
+        hipLaunchKernelGGL(k_relu_bwd, dim3(ge), dim3(256), 0, st, ne, dXe_above, 192, 128, v.dXn, v.dst, v.Zm[l],
+                           v.dZ, v.bpart);
+        hipLaunchKernelGGL(k_bias_sum, dim3(D), dim3(256), 0, st, v.bpart, int(ge), gl + kBm);
         Seg xe{{v.H[l], v.H[l], v.M[l]}, {v.src, v.dst, nullptr}};
         hipLaunchKernelGGL(k_wgrad<3>, dim3(blocks_for(ne, kRowsPerBlock)), dim3(256), 0, st, ne, v.dZ, xe,
                            gl + kWm);
