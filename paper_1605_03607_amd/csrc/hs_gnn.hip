@@ -186,25 +186,31 @@ __global__ void __launch_bounds__(256) k_wgrad(int rows, const uint16_t *dZ, Seg
         for (int j = 0; j < NSEG; ++j) acc[mb][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int rbeg = blockIdx.x * kRowsPerBlock;
     const int rend = min(rows, rbeg + kRowsPerBlock);
-    for (int r0 = rbeg; r0 < rend; r0 += 32) {
-        // stage 32 rows of dZ (32 x 64) and of X (32 x 64 NSEG), 16 bytes per thread and chunk
-        {
-            const int rr = tid >> 3, ch = tid & 7;  // row in slice, 16-byte chunk in a 64-wide row
-            const int r = r0 + rr;
-            uint4 z = {0u, 0u, 0u, 0u};
-            if (r < rend) z = *reinterpret_cast<const uint4 *>(dZ + int64_t(r) * D + ch * 8);
-            *reinterpret_cast<uint4 *>(zt + rr * D + ch * 8) = z;
+    // 32-row slices of dZ (32 x 64) and of X (32 x 64 NSEG), 16 bytes per
+    // thread and chunk; the next slice is loaded into registers while the
+    // current one is multiplied out of LDS
+    const int rr = tid >> 3, ch = tid & 7;  // row in slice, 16-byte chunk in a 64-wide row
+    uint4 zn, xn[NSEG];
+    auto fetch = [&](int r0) {
+        const int r = r0 + rr;
+        zn = uint4{0u, 0u, 0u, 0u};
+        if (r < rend) zn = *reinterpret_cast<const uint4 *>(dZ + int64_t(r) * D + ch * 8);
 #pragma unroll
-            for (int s = 0; s < NSEG; ++s) {
-                uint4 x = {0u, 0u, 0u, 0u};
-                if (r < rend) {
-                    const int64_t src = X.idx[s] ? int64_t(X.idx[s][r]) : int64_t(r);
-                    x = *reinterpret_cast<const uint4 *>(X.base[s] + src * D + ch * 8);
-                }
-                *reinterpret_cast<uint4 *>(xt + rr * K + s * 64 + ch * 8) = x;
+        for (int s = 0; s < NSEG; ++s) {
+            xn[s] = uint4{0u, 0u, 0u, 0u};
+            if (r < rend) {
+                const int64_t src = X.idx[s] ? int64_t(X.idx[s][r]) : int64_t(r);
+                xn[s] = *reinterpret_cast<const uint4 *>(X.base[s] + src * D + ch * 8);
             }
         }
+    };
+    if (rbeg < rend) fetch(rbeg);
+    for (int r0 = rbeg; r0 < rend; r0 += 32) {
+        *reinterpret_cast<uint4 *>(zt + rr * D + ch * 8) = zn;
+#pragma unroll
+        for (int s = 0; s < NSEG; ++s) *reinterpret_cast<uint4 *>(xt + rr * K + s * 64 + ch * 8) = xn[s];
         __syncthreads();
+        if (r0 + 32 < rend) fetch(r0 + 32);
         bf16x8 a[4];
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
