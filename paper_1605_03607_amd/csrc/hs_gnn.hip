@@ -277,27 +277,38 @@ __global__ void k_gather_sum(const uint16_t *M, const int32_t *outE, uint16_t *S
     *reinterpret_cast<uint4 *>(S + v * D + c * 8) = o;
 }
 
-// One workgroup (256 threads) per graph: mean of the live h rows, y_hat.
-__global__ void __launch_bounds__(256) k_readout(const uint16_t *H, const float *live, const float *nlive,
-                                                 const float *P, float *mean, float *y, int n)
+// Readout in two passes.  k_readout_part: workgroup (g, p) sums the live h
+// rows of nodes [p n / S, (p + 1) n / S) of graph g (S = kReadSplit) into
+// rpart[g][p][64].  k_readout_fin: 64 threads per graph add the S partial
+// sums in order, take the mean over live nodes and form y_hat.
+constexpr int kReadSplit = 8;
+__global__ void __launch_bounds__(256) k_readout_part(const uint16_t *H, const float *live, int n, float *rpart)
 {
     __shared__ float part[4][D];
-    __shared__ float red[D];
-    const int g = blockIdx.x, t = threadIdx.x, d = t & 63, q = t >> 6;
+    const int g = blockIdx.x, p = blockIdx.y, t = threadIdx.x, d = t & 63, q = t >> 6;
+    const int lo = int(int64_t(p) * n / kReadSplit), hi = int(int64_t(p + 1) * n / kReadSplit);
     float s = 0.f;
-    for (int v = q; v < n; v += 4) {
+    for (int v = lo + q; v < hi; v += 4) {
         const int64_t row = int64_t(g) * n + v;
         s += live[row] * bf2f(H[row * D + d]);
     }
     part[q][d] = s;
     __syncthreads();
-    if (t < D) {
-        const float m = (part[0][d] + part[1][d] + part[2][d] + part[3][d]) / nlive[g];
-        mean[g * D + d] = m;
-        red[d] = m * P[kWout + d];
-    }
+    if (t < D) rpart[(int64_t(g) * kReadSplit + p) * D + d] = part[0][d] + part[1][d] + part[2][d] + part[3][d];
+}
+
+__global__ void __launch_bounds__(64) k_readout_fin(const float *rpart, const float *nlive, const float *P,
+                                                    float *mean, float *y)
+{
+    __shared__ float red[D];
+    const int g = blockIdx.x, d = threadIdx.x;
+    float s = 0.f;
+    for (int p = 0; p < kReadSplit; ++p) s += rpart[(int64_t(g) * kReadSplit + p) * D + d];
+    const float m = s / nlive[g];
+    mean[g * D + d] = m;
+    red[d] = m * P[kWout + d];
     __syncthreads();
-    if (t == 0) {
+    if (d == 0) {
         float acc = P[kBout];
         for (int k = 0; k < D; ++k) acc += red[k];
         y[g] = acc;
@@ -407,8 +418,11 @@ __global__ void k_node_collect(const float *dXn, const float *dXe, const int32_t
 // Embedding gradients: node (W_en, b_en) from dH0, edge (W_ee, b_ee) from
 // dM0 = column 128.. of the first layer's edge input gradient, summed over
 // the two directions of each coupler.
+// Workgroup (x, y) of a kEmbBlocks x 2 grid (y = 0 nodes, 1 couplers) stores
+// its partial sums in epart[y][x][64][6]; k_embed_sum adds them up.
+constexpr int kEmbBlocks = 512;
 __global__ void __launch_bounds__(256) k_embed_bwd(const float *dH0, const float *dXe0, const float *xn,
-                                                   const float *xe, int nn, int nq, float *grad)
+                                                   const float *xe, int nn, int nq, float *epart)
 {
     __shared__ float part[4][D][6];
     const int t = threadIdx.x, d = t & 63, q = t >> 6;
@@ -429,14 +443,36 @@ __global__ void __launch_bounds__(256) k_embed_bwd(const float *dH0, const float
     for (int f = 0; f < 6; ++f) part[q][d][f] = a[f];
     __syncthreads();
     if (t < D) {
-        float s[6];
-        for (int f = 0; f < 6; ++f) s[f] = part[0][d][f] + part[1][d][f] + part[2][d][f] + part[3][d][f];
-        if (blockIdx.y == 0) {
-            for (int f = 0; f < kNodeF; ++f) atomicAdd(&grad[kWen + d * kNodeF + f], s[f]);
-            atomicAdd(&grad[kBen + d], s[5]);
+        float *o = epart + ((int64_t(blockIdx.y) * gridDim.x + blockIdx.x) * D + d) * 6;
+        for (int f = 0; f < 6; ++f) o[f] = part[0][d][f] + part[1][d][f] + part[2][d][f] + part[3][d][f];
+    }
+}
+
+// Embedding gradients from the partial sums: workgroup (d, y) adds the nb
+// workgroups' 6 sums of feature d with a fixed tree.
+__global__ void __launch_bounds__(256) k_embed_sum(const float *epart, int nb, float *grad)
+{
+    __shared__ float red[6][256];
+    const int d = blockIdx.x, y = blockIdx.y, t = threadIdx.x;
+    float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int b = t; b < nb; b += 256) {
+        const float *p = epart + ((int64_t(y) * nb + b) * D + d) * 6;
+        for (int f = 0; f < 6; ++f) s[f] += p[f];
+    }
+    for (int f = 0; f < 6; ++f) red[f][t] = s[f];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int f = 0; f < 6; ++f) red[f][t] += red[f][t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (y == 0) {
+            for (int f = 0; f < kNodeF; ++f) grad[kWen + d * kNodeF + f] += red[f][0];
+            grad[kBen + d] += red[5][0];
         } else {
-            for (int f = 0; f < kEdgeF; ++f) atomicAdd(&grad[kWee + d * kEdgeF + f], s[f]);
-            atomicAdd(&grad[kBee + d], s[5]);
+            for (int f = 0; f < kEdgeF; ++f) grad[kWee + d * kEdgeF + f] += red[f][0];
+            grad[kBee + d] += red[5][0];
         }
     }
 }
@@ -466,7 +502,8 @@ namespace {
 struct Layout {
     int G = 0, L = 0, N = 0, E = 0;
     int64_t nn = 0, nq = 0, ne = 0;
-    size_t xn, xe, live, nlive, src, dst, outE, wb, H, M, S, Zm, Zh, mean, y, dy, dZ, dXe, dXn, dH, bpart, total;
+    size_t xn, xe, live, nlive, src, dst, outE, wb, H, M, S, Zm, Zh, mean, y, dy, dZ, dXe, dXn, dH, bpart, rpart,
+        epart, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -508,6 +545,8 @@ bool make_layout(int G, int L, Layout &o)
     o.dXn = take(size_t(o.nn) * 128 * 4);
     o.dH = take(size_t(o.nn) * D * 4);
     o.bpart = take(size_t(kReluBlocks) * D * 4);
+    o.rpart = take(size_t(G) * kReadSplit * D * 4);
+    o.epart = take(size_t(2) * kEmbBlocks * D * 6 * 4);
     o.total = p;
     return true;
 }
@@ -515,7 +554,7 @@ bool make_layout(int G, int L, Layout &o)
 int hip_err(hipError_t e, const char *what) { return fail(HS_EHIP, std::string(what) + ": " + hipGetErrorString(e)); }
 
 struct Bufs {
-    float *xn, *xe, *live, *nlive, *mean, *y, *dy, *dXe[2], *dXn, *dH, *bpart, *Zm[kLayers], *Zh[kLayers];
+    float *xn, *xe, *live, *nlive, *mean, *y, *dy, *dXe[2], *dXn, *dH, *bpart, *rpart, *epart, *Zm[kLayers], *Zh[kLayers];
     int32_t *src, *dst, *outE;
     uint16_t *H[kLayers + 1], *M[kLayers + 1], *S[kLayers], *dZ;
     WeightsBf wb;
@@ -561,6 +600,8 @@ Bufs views(const Layout &o, void *ws)
     v.dXn = reinterpret_cast<float *>(b + o.dXn);
     v.dH = reinterpret_cast<float *>(b + o.dH);
     v.bpart = reinterpret_cast<float *>(b + o.bpart);
+    v.rpart = reinterpret_cast<float *>(b + o.rpart);
+    v.epart = reinterpret_cast<float *>(b + o.epart);
     return v;
 }
 
@@ -586,8 +627,9 @@ int forward_pass(const float *P, const Layout &o, const Bufs &v, hipStream_t st,
         hipLaunchKernelGGL((k_rows<2, 4>), dim3(blocks_for(nn, 64)), dim3(256), 0, st, nn, xn, v.wb.wh[l],
                            Ls + kBh, keep_z ? v.Zh[l] : nullptr, v.H[l + 1]);
     }
-    hipLaunchKernelGGL(k_readout, dim3(o.G), dim3(256), 0, st, v.H[kLayers], v.live, v.nlive, P, v.mean, v.y,
-                       o.N);
+    hipLaunchKernelGGL(k_readout_part, dim3(o.G, kReadSplit), dim3(256), 0, st, v.H[kLayers], v.live, o.N,
+                       v.rpart);
+    hipLaunchKernelGGL(k_readout_fin, dim3(o.G), dim3(64), 0, st, v.rpart, v.nlive, P, v.mean, v.y);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? HS_OK : hip_err(e, "gnn forward: launch");
 }
@@ -746,8 +788,9 @@ int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labe
         dXe_above = v.dXe[cur];
         cur ^= 1;
     }
-    hipLaunchKernelGGL(k_embed_bwd, dim3(64, 2), dim3(256), 0, st, v.dH, dXe_above, v.xn, v.xe, nn, int(o.nq),
-                       grad);
+    hipLaunchKernelGGL(k_embed_bwd, dim3(kEmbBlocks, 2), dim3(256), 0, st, v.dH, dXe_above, v.xn, v.xe, nn,
+                       int(o.nq), v.epart);
+    hipLaunchKernelGGL(k_embed_sum, dim3(D, 2), dim3(256), 0, st, v.epart, kEmbBlocks, grad);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_err(e, "gnn_train_step: launch");
     if (y_hat) {
