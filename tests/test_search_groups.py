@@ -200,3 +200,13 @@ def test_resume_after_a_killed_process(S, tmp_path):
     assert back.decisions == full.decisions
     assert np.array_equal(back.ln, full.ln)
     assert back.hard == full.hard
+
+
+def test_checkpoint_needs_groups_at_one_step(S, tmp_path):
+    cfg = S.SearchConfig(mode="plain", chains=4, L=2)
+    seeds = [workloads.couplings(2, "pm1", 73, c) for c in range(4)]
+    run = S.GroupedSearch(cfg, seeds, groups=2)
+    run.run(1)
+    run.groups[1].run_step()
+    with pytest.raises(ValueError, match="different steps"):
+        S.save_search(run, str(tmp_path / "x.npz"))
