@@ -90,7 +90,9 @@ typedef struct hs_pt_desc {
     uint32_t seed;           /* second word of every Philox key */
     int32_t swap_interval;   /* exchange pass after every swap_interval-th sweep; 0 = none */
     uint32_t flags;          /* HS_INIT_FROM_BUFFER | HS_STOP_ON_AGREEMENT */
-    int32_t block_waves;     /* wavefronts per instance (1..16); 0 = chosen by the tuner */
+    int32_t block_waves;     /* wavefronts per instance (1..16); 0 = one per cell pair of the
+                                largest instance, rounded up to a power of two, at most 16
+                                (pt_autotune measures the candidates instead) */
 } hs_pt_desc;
 
 /* Device buffers of a batch (caller-owned; offsets per instance n):
@@ -191,15 +193,24 @@ int pt_swap(hs_pt *h);
  * lane differs; *n_mismatch (host, may be NULL) receives the count. */
 int pt_measure(hs_pt *h, int32_t *recomputed, int32_t *n_mismatch);
 
-/* Frees the host handle (device buffers stay the caller's). */
+/* Frees the host handle (device buffers stay the caller's).  Waits until the
+ * workspace upload that pt_init enqueued has finished (it reads the handle's
+ * host staging copy), not for later work on the stream.  NULL is a no-op. */
 int pt_destroy(hs_pt *h);
+
+/* Launch shape of the handle's persistent sweep kernel: workgroups in the
+ * grid (at most n_inst; each takes instances from the work queue until it is
+ * empty), wavefronts per workgroup and dynamic LDS bytes per workgroup.  Any
+ * output pointer may be NULL.  Host only. */
+int pt_launch_shape(const hs_pt *h, int32_t *grid, int32_t *block_waves, int32_t *lds_bytes);
 
 /* One RAO move (Algorithm 1, Sec. II.A) as a pure host function.
  * (w0, w1, w2, w3) = Philox((chain, seed), (step, proposal, 0, 4)); the
  * coupler is the e-th live one in canonical order, e = floor(w0 E_live /
  * 2^32); the new value is entry floor(w1 (n_alpha - 1) / 2^32) of the
  * ascending alphabet with the current value removed (a sign flip for
- * {-1, +1}).  `in` is not modified. */
+ * {-1, +1}).  `in` is not modified.  HS_EINVAL when the alphabet repeats a
+ * value or does not hold the chosen coupler's current value. */
 typedef struct hs_mutation {
     int32_t edge;       /* index in the full canonical coupler list */
     int8_t old_j;

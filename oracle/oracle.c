@@ -37,11 +37,15 @@
  *   ground state (Appendix B's run time per find of the minimum).
  *
  * Parity status: every function here is pinned by the not-gpu tests
- * (brute force, closed forms, Boltzmann statistics, gauge invariance,
- * rocRAND's independent Philox) EXCEPT the numerical value of the
- * time-to-solution and of search outcomes: "parity unpinned" for
- * or_hardness_eval's TTS values and for or_mutate's choices beyond the
- * invariants of Algorithm 1.
+ * against things other than itself: brute force, closed forms, Boltzmann
+ * statistics (one and two cells, and the joint slot / configuration
+ * distribution of PT), gauge invariance, Random123 known-answer vectors and
+ * rocRAND's independent Philox, thresholds against 50-digit exponentials,
+ * and for or_hardness_eval a zero-temperature limit recomputed from the
+ * definitions (greedy descent, agreement stop, TTS) plus the free-coupling
+ * closed form.  or_mutate's draws are pinned by their joint uniformity over
+ * (live coupler, other letter).  Search trajectories as a whole are pinned
+ * only through these parts.
  */
 #include <math.h>
 #include <stdint.h>
@@ -632,7 +636,10 @@ int or_mutate(int L, const uint8_t *live, const int8_t *J, const int8_t *alphabe
               uint32_t chain, uint32_t seed, uint32_t step, uint32_t proposal, int32_t *edge,
               int8_t *old_j, int8_t *new_j, uint32_t *w_accept)
 {
-    if (n_alpha < 2) return -1;
+    if (n_alpha < 2 || n_alpha > 255) return -1;
+    for (int a = 0; a < n_alpha; ++a)
+        for (int b = 0; b < a; ++b)
+            if (alphabet[a] == alphabet[b]) return -1; /* the alphabet is a set */
     Inst *g = inst_new(L, live, J);
     if (!g) return -1;
     uint32_t ctr[4] = {step, proposal, 0u, OR_D_MUTATE};
@@ -661,8 +668,12 @@ int or_mutate(int L, const uint8_t *live, const int8_t *J, const int8_t *alphabe
     int nr = 0;
     for (int a = 0; a < n_alpha; ++a)
         if (alphabet[a] != cur) rest[nr++] = alphabet[a];
-    /* if the current value is not in the alphabet every value is allowed;
-       the index is still drawn over |A| - 1 choices */
+    /* the move replaces the current value by another value of the alphabet,
+       so the current value must be one of its letters */
+    if (nr != n_alpha - 1) {
+        inst_free(g);
+        return -1;
+    }
     int idx = (int)(((uint64_t)w[1] * (uint64_t)(n_alpha - 1)) >> 32);
     *edge = e_sel;
     *old_j = cur;

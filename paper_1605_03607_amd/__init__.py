@@ -107,6 +107,8 @@ def lib():
         L.pt_swap.argtypes = [C.c_void_p]
         L.pt_measure.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
         L.pt_destroy.argtypes = [C.c_void_p]
+        L.pt_launch_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]
         L.pt_graph_create.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_void_p)]
         L.pt_graph_launch.argtypes = [C.c_void_p]
         L.pt_graph_destroy.argtypes = [C.c_void_p]
@@ -159,7 +161,7 @@ def exported_symbols():
             "pt_autotune", "instance_mutate", "hs_rao_accept", "hardness_workspace_bytes",
             "hardness_eval", "gnn_param_count", "gnn_workspace_bytes", "gnn_prepare", "gnn_forward",
             "gnn_train_step", "pt_sweep_record", "walk_autocorr", "walk_tau", "lao_cycle_count", "lao_init",
-            "lao_move", "pt_capture", "overlap_analyze"]
+            "lao_move", "pt_capture", "overlap_analyze", "pt_launch_shape"]
 
 
 def _check(rc):
@@ -268,6 +270,13 @@ class PTBatch:
 
     def swap(self):
         _check(lib().pt_swap(self.h))
+
+    def launch_shape(self):
+        """(workgroups in the grid, wavefronts per workgroup, LDS bytes per
+        workgroup) of the persistent sweep launch."""
+        g, w, b = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        _check(lib().pt_launch_shape(self.h, C.byref(g), C.byref(w), C.byref(b)))
+        return g.value, w.value, b.value
 
     def measure(self):
         """Recomputes energies on the device; returns the mismatch count."""

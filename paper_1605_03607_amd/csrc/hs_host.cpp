@@ -195,7 +195,11 @@ uint64_t swap_threshold(double beta_lo, double beta_hi, int64_t d)
     return uint64_t(std::floor(std::ldexp(x, 32)));
 }
 
-void build_tables(int K, const double *beta, HostTables &t)
+// d_cap bounds the exchange tables: no two configurations of any instance
+// using this ladder differ in energy by more than d_cap (2 sum |J| over its
+// live couplers), so entries beyond it are never read and a closely spaced
+// ladder cannot make the table grow without bound.
+void build_tables(int K, const double *beta, int64_t d_cap, HostTables &t)
 {
     t.K = K;
     t.beta.assign(beta, beta + K);
@@ -223,7 +227,7 @@ void build_tables(int K, const double *beta, HostTables &t)
         t.ts_row[k] = int32_t(t.ts_hi.size());
         t.ts_full_row[k] = int32_t(t.ts_full.size());
         int64_t d = 1;
-        for (;; ++d) {
+        for (; d <= d_cap; ++d) {
             const uint64_t T = swap_threshold(beta[k], beta[k + 1], d);
             if (T == 0) break;
             t.ts_full.push_back(uint32_t(T));
@@ -255,6 +259,9 @@ int instance_mutate(const hs_instance *in, const int8_t *alphabet, int n_alpha, 
         return fail(HS_EINVAL, "instance_mutate: bad arguments");
     if (in->L < 1 || in->L > HS_MAX_L || in->J == nullptr)
         return fail(HS_EINVAL, "instance_mutate: bad instance");
+    for (int a = 0; a < n_alpha; ++a)
+        for (int b = 0; b < a; ++b)
+            if (alphabet[a] == alphabet[b]) return fail(HS_EINVAL, "instance_mutate: repeated alphabet value");
     std::vector<int32_t> ei, ej;
     chimera_edges(in->L, ei, ej);
     auto live = [&](int i) { return in->live == nullptr || in->live[i] != 0; };
@@ -272,6 +279,11 @@ int instance_mutate(const hs_instance *in, const int8_t *alphabet, int n_alpha, 
     std::vector<int8_t> rest;
     for (int a = 0; a < n_alpha; ++a)
         if (alphabet[a] != cur) rest.push_back(alphabet[a]);
+    // the alphabet minus the current value must have n_alpha - 1 entries:
+    // distinct letters, one of them the current value
+    if (rest.size() + 1 != size_t(n_alpha))
+        return fail(HS_EINVAL, "instance_mutate: the alphabet must hold distinct values, one of them the "
+                               "coupler's current value");
     const size_t idx = size_t((uint64_t(w[1]) * uint64_t(n_alpha - 1)) >> 32);
     out->edge = e;
     out->old_j = cur;

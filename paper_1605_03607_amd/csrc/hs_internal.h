@@ -80,7 +80,7 @@ struct HostInstance {
 // Host-side builders (hs_host.cpp).
 void chimera_edges(int L, std::vector<int32_t> &ei, std::vector<int32_t> &ej);
 int build_instance(const hs_instance &in, HostInstance &out, std::string &err);
-void build_tables(int K, const double *beta, HostTables &out);
+void build_tables(int K, const double *beta, int64_t d_cap, HostTables &out);
 void build_tasks(int L, int nwaves, std::vector<uint32_t> &out, int &iters);
 uint64_t metro_threshold(double beta, int m);
 uint64_t swap_threshold(double beta_lo, double beta_hi, int64_t d);

@@ -1022,6 +1022,7 @@ struct hs_pt {
     // workspace layout (byte offsets)
     size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0;
     std::vector<uint32_t> host_ws;  // staging image of the workspace (kept until destroy)
+    hipEvent_t uploaded = nullptr;  // recorded after the upload of host_ws on `stream`
 };
 
 namespace {
@@ -1098,6 +1099,9 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
     const int n = d.n_inst;
     P.hi.resize(n);
     P.tab_of.resize(n);
+    // largest energy difference between two configurations of any instance:
+    // 2 sum |J| over its live couplers (bounds the exchange tables)
+    int64_t d_cap = 0;
     for (int i = 0; i < n; ++i) {
         const hs_instance &in = d.inst[i];
         int rc = validate_inst(in, err);
@@ -1108,6 +1112,12 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
             err = "HS_STOP_ON_AGREEMENT needs R >= 2";
             return HS_EINVAL;
         }
+        int64_t sum_j = 0;
+        for (uint32_t e : P.hi[i].edges) sum_j += std::abs(int(int8_t(uint8_t(e >> 24))));
+        d_cap = std::max(d_cap, 2 * sum_j);
+    }
+    for (int i = 0; i < n; ++i) {
+        const hs_instance &in = d.inst[i];
         // share tables between instances with the same ladder
         int found = -1;
         for (size_t t = 0; t < P.ht.size(); ++t)
@@ -1117,7 +1127,7 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
             }
         if (found < 0) {
             P.ht.emplace_back();
-            build_tables(in.K, in.beta, P.ht.back());
+            build_tables(in.K, in.beta, d_cap, P.ht.back());
             if (P.ht.back().ts_full.size() > (size_t(1) << 24)) {
                 err = "temperature ladder too dense for the exchange tables";
                 return HS_EUNSUPPORTED;
@@ -1319,8 +1329,10 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
     }
     hipError_t e = hipMemcpyAsync(b->workspace, h->host_ws.data(), h->host_ws.size() * 4,
                                   hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->uploaded, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(h->uploaded, h->stream);
     if (e != hipSuccess) {
-        delete h;
+        pt_destroy(h);
         return hip_fail(e, "pt_init: upload");
     }
     const char *ws = reinterpret_cast<const char *>(b->workspace);
@@ -1339,7 +1351,7 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
     hipLaunchKernelGGL(dev::k_pt_init, dim3(h->n_inst), dim3(64), 0, h->stream, ia);
     e = hipGetLastError();
     if (e != hipSuccess) {
-        delete h;
+        pt_destroy(h);
         return hip_fail(e, "pt_init: launch");
     }
     const void *kfn = reinterpret_cast<const void *>(&dev::k_pt_sweep<false>);
@@ -1349,14 +1361,14 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
         if (e == hipSuccess)
             e = hipFuncSetAttribute(kfn_rec, hipFuncAttributeMaxDynamicSharedMemorySize, int(h->lds_bytes));
         if (e != hipSuccess) {
-            delete h;
+            pt_destroy(h);
             return hip_fail(e, "pt_init: LDS size");
         }
     }
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, h->nwaves * 64, h->lds_bytes);
     if (e != hipSuccess || per_cu < 1) {
-        delete h;
+        pt_destroy(h);
         return fail(HS_EUNSUPPORTED, "pt_init: instances too large for one workgroup's LDS");
     }
     h->grid = std::min(h->n_inst, per_cu * device_cus());
@@ -1593,7 +1605,24 @@ int pt_capture(hs_pt *h, const int32_t *e_cap, uint64_t *configs, int32_t *meta,
 
 int pt_destroy(hs_pt *h)
 {
+    if (h == nullptr) return HS_OK;
+    int rc = HS_OK;
+    if (h->uploaded != nullptr) {
+        // the upload reads host_ws asynchronously: wait for it before freeing
+        const hipError_t e = hipEventSynchronize(h->uploaded);
+        if (e != hipSuccess) rc = hip_fail(e, "pt_destroy: waiting for the workspace upload");
+        (void)hipEventDestroy(h->uploaded);
+    }
     delete h;
+    return rc;
+}
+
+int pt_launch_shape(const hs_pt *h, int32_t *grid, int32_t *block_waves, int32_t *lds_bytes)
+{
+    if (h == nullptr) return fail(HS_EINVAL, "pt_launch_shape: NULL handle");
+    if (grid) *grid = h->grid;
+    if (block_waves) *block_waves = h->nwaves;
+    if (lds_bytes) *lds_bytes = int32_t(h->lds_bytes);
     return HS_OK;
 }
 

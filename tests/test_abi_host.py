@@ -254,3 +254,49 @@ def test_lao_moves_keep_the_cap_and_match_oracle_on_dense_c4():
         J, e = P.couplings(4, o["loops"], cyc, o["bits"])
         assert np.array_equal(J, a[3]) and e == a[4]
     assert voids > 0
+
+
+def test_mutation_rejects_alphabets_that_are_not_sets_holding_the_value():
+    """Algorithm 1 replaces a coupler's value by another value of the
+    alphabet: an alphabet with a repeated letter, or one without the chosen
+    coupler's current value, is an error in the library and in the oracle
+    (never an out-of-range read)."""
+    hs = _hs()
+    L = 2
+    J = workloads.couplings(L, "pm1", 3, 0)
+    inst = dict(L=L, J=J, live=None)
+    bad = [np.array([-1, 1, 1], np.int8), np.array([-1, -1], np.int8), np.array([2, 3, 4], np.int8)]
+    for A in bad:
+        with pytest.raises(RuntimeError):
+            hs.instance_mutate(inst, A, 0, 1, 0, 0)
+        with pytest.raises(ValueError):
+            oracle.mutate(L, None, J, A, 0, 1, 0, 0)
+    good = np.array([-1, 1], np.int8)
+    assert hs.instance_mutate(inst, good, 0, 1, 0, 0) == oracle.mutate(L, None, J, good, 0, 1, 0, 0)
+
+
+def test_closely_spaced_ladder_keeps_the_exchange_table_bounded():
+    """Exchange thresholds are tabulated only up to the largest energy
+    difference an instance allows (2 sum |J|): a ladder with a spacing of
+    1e-9 (where floor(2^32 e^{-d dbeta}) stays positive for ~2e10 entries)
+    is accepted at once with a small workspace."""
+    hs = _hs()
+    import ctypes as C
+    import time
+    L = 4
+    J = workloads.couplings(L, "pm7", 5, 0)
+    d = dict(L=L, J=J, live=None, K=2, R=1, beta=np.array([1.0, 1.0 + 1e-9]), instance_id=0)
+    hi = hs._HostInstances([d])
+    desc = hs.hs_pt_desc(1, C.cast(hi.arr, C.POINTER(hs.hs_instance)), 1, 1, 0, 0)
+    nb = C.c_size_t(0)
+    t0 = time.perf_counter()
+    assert hs.lib().pt_workspace_bytes(C.byref(desc), C.byref(nb)) == 0
+    assert time.perf_counter() - t0 < 5.0
+    two_sum_j = 2 * int(np.abs(J.astype(np.int64)).sum())
+    assert nb.value < 64 * 1024 + 8 * two_sum_j
+
+
+def test_destroy_of_a_null_handle_is_a_no_op():
+    hs = _hs()
+    assert hs.lib().pt_destroy(None) == 0
+    assert hs.lib().pt_launch_shape(None, None, None, None) == -1
