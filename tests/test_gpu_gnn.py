@@ -13,7 +13,10 @@ Tolerances (relative L2 norm of the difference):
     1e-3.  Both sides then multiply the same BF16 numbers; they differ only by
     FP32 versus FP64 accumulation (~1e-7 relative) and by the rare BF16
     rounding flips this causes (one flip moves one element by 2^-8), which
-    leave the L2 error orders of magnitude below 1e-3."""
+    leave the L2 error orders of magnitude below 1e-3.
+  * element by element against the BF16-rounding oracle: every output and
+    every gradient entry within 4 x 2^-8 of the largest magnitude in its
+    block, so a few wrong elements cannot hide under a block's L2 norm."""
 import numpy as np
 import pytest
 
@@ -51,6 +54,18 @@ def _rel(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+# element-wise bound, in units of 2^-8 times the block's largest magnitude
+ELEM_C = 4.0
+
+
+def _elem(a, b):
+    """max |a - b| over a block in units of 2^-8 max |b|."""
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    scale = max(float(np.abs(b).max()), 1e-30)
+    return float(np.abs(a - b).max() / (scale * 2.0 ** -8))
 
 
 def _blocks(theta):
@@ -91,6 +106,14 @@ def test_forward_and_gradients_match_oracle(L, n, missing):
     for name in b_gpu:
         assert _rel(b_gpu[name], b64[name]) < tol64, (name, _rel(b_gpu[name], b64[name]))
         assert _rel(b_gpu[name], bbf[name]) < 1e-3, (name, _rel(b_gpu[name], bbf[name]))
+    # element by element against the BF16-rounding oracle: every output and
+    # every gradient entry within ELEM_C * 2^-8 of its block's largest
+    # magnitude (one BF16 rounding flip moves one operand by 2^-8 relative)
+    worst = max(_elem(y, ybf), *(_elem(b_gpu[n], bbf[n]) for n in b_gpu))
+    print(f"element-wise: worst |gpu - bf16 oracle| / (2^-8 block max) = {worst:.3f}", flush=True)
+    assert _elem(y, ybf) < ELEM_C, _elem(y, ybf)
+    for name in b_gpu:
+        assert _elem(b_gpu[name], bbf[name]) < ELEM_C, (name, _elem(b_gpu[name], bbf[name]))
 
 
 def test_adam_update_matches_oracle():
