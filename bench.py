@@ -25,16 +25,16 @@ sys.path.insert(0, ROOT)
 
 import workloads  # noqa: E402
 
-# Integer VALU peak of MI355X derived from its published vector figures:
-# 157.3 TFLOP/s fp32 vector = 256 CUs x 128 FMA lanes/clock x 2.4 GHz x 2 flop,
-# i.e. 7.86e13 32-bit lane operations per second.
-PEAK_INT32_OPS = 157.3e12 / 2
-# Algorithmic 32-bit lane operations per spin-flip attempt of the implemented
-# formulation: Philox4x32-10 serves 8 attempts (16-bit uniforms) with 10 rounds
-# of 2 full 32x32->64 products (2 ops each) and 2 three-input xors -> 60 / 8 =
-# 7.5; local field: two 4-way byte dot products and one multiply = 3;
-# decision: threshold address, compare, energy select and add, flip = 5.
-A_OPS = 10 * (2 * 2 + 2) / 8 + 3 + 5
+# Op count and peak of the sweep kernel's roofline (integer VALU issue), fixed
+# in roofline_opcount.json: the reported frac uses the reference count (22 ops
+# per attempt, the minimal formulation fixed before tuning); the count of the
+# formulation this kernel runs (15.5) is reported beside it.
+with open(os.path.join(ROOT, "roofline_opcount.json")) as _f:
+    OPCOUNT = json.load(_f)
+PEAK_INT32_OPS = float(OPCOUNT["peak_lane_ops_per_s"])
+A_OPS = float(OPCOUNT["reference"]["ops_per_attempt"])
+A_OPS_IMPL = float(OPCOUNT["implemented"]["ops_per_attempt"])
+ISSUE_RATES_FILE = os.path.join(ROOT, "profiles", "isa_issue_rates.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1605_03607_amd", "csrc", "hs_pt.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pt_sweep_c8x256_traffic.json")
 
@@ -103,8 +103,7 @@ def cpu_baseline(cfg, insts, budget_s):
     """The CPU oracle, as it stands, on the host's cores: one instance per
     thread, a prefix of the sweeps, scaled to attempts/s."""
     import oracle
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 16))
+    cores = host_cores()
     lanes = cfg["K"] * cfg["R"]
     n_sites = 8 * cfg["L"] ** 2
     # calibrate: one instance, a few sweeps
@@ -138,9 +137,62 @@ def cpu_baseline(cfg, insts, budget_s):
                       f"{el:.1f} s wall"}
 
 
-def host_cores(limit=16):
+# Host threads the CPU baselines use at most: a one-GPU machine's CPU share is 16
+# threads, whatever count the operating system reports for the whole machine.
+HOST_THREAD_CAP = 16
+
+
+def host_cores(limit=HOST_THREAD_CAP):
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return max(1, min(cores, limit))
+
+
+def host_info():
+    """What the host reports about its CPUs, recorded with every CPU baseline."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"host_cpu_model": model, "host_nproc": os.cpu_count(), "host_affinity_cpus": aff,
+            "thread_cap": HOST_THREAD_CAP,
+            "thread_cap_reason": "a one-GPU box's CPU share is 16 threads; cores = min(affinity CPUs, cap, "
+                                 "instances in the sample)"}
+
+
+def emit(line):
+    """Prints the benchmark's JSON line; a CPU baseline carries what the host
+    reports about its CPUs."""
+    if isinstance(line.get("cpu_baseline"), dict):
+        line["cpu_baseline"].update(host_info())
+    print(json.dumps(line), flush=True)
+
+
+def measured_issue_rates():
+    """Issue rates of single instruction classes measured on the box
+    (bench.py --probe), from the committed summary, or None."""
+    try:
+        with open(ISSUE_RATES_FILE) as f:
+            return json.load(f).get("lane_ops_per_s")
+    except (OSError, ValueError):
+        return None
+
+
+def alu_roofline(attempts, kernel_s):
+    """The int32-VALU roofline fields of a sweep-kernel launch: achieved
+    lane operations per second at the reference op count, its fraction of
+    the peak, and the same at the implemented op count."""
+    per_s = attempts / kernel_s if kernel_s > 0 else 0.0
+    return {"bound": "alu", "achieved": per_s * A_OPS / 1e12, "peak": PEAK_INT32_OPS / 1e12,
+            "unit": "Tops/s (int32 lane operations)", "frac": per_s * A_OPS / PEAK_INT32_OPS,
+            "ops_per_attempt": A_OPS, "ops_per_attempt_implemented": A_OPS_IMPL,
+            "frac_implemented_ops": per_s * A_OPS_IMPL / PEAK_INT32_OPS,
+            "peak_derivation": OPCOUNT["peak_derivation"], "opcount_file": "roofline_opcount.json"}
 
 
 def pt_roofline(attempts, kernel_ms, launches, kernel, wall_s=None):
@@ -150,11 +202,9 @@ def pt_roofline(attempts, kernel_ms, launches, kernel, wall_s=None):
     launch duration.  With wall_s, also the whole chip's share over that
     wall time (launches of concurrent groups overlap, so their durations
     add up to more than the time they span)."""
-    achieved = attempts * A_OPS / (kernel_ms / 1e3) if kernel_ms > 0 else 0.0
-    out = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
-           "unit": "Tops/s (int32 lane operations)", "frac": achieved / PEAK_INT32_OPS, "traffic": None,
-           "kernel_ms_avg": kernel_ms / max(1, launches), "launches": launches, "ops_per_attempt": A_OPS,
-           "kernel": kernel}
+    out = alu_roofline(attempts, kernel_ms / 1e3)
+    out.update({"traffic": None, "kernel_ms_avg": kernel_ms / max(1, launches), "launches": launches,
+                "kernel": kernel})
     if wall_s:
         out["chip_frac_over_wall"] = attempts * A_OPS / wall_s / PEAK_INT32_OPS
         out["wall_s"] = wall_s
@@ -319,7 +369,6 @@ def uneven(args):
     mism = batch.measure()
     attempts = live_per_sweep * sweeps
     k_avg_s = float(np.mean(kernel_ms)) / 1e3
-    achieved = attempts * A_OPS / k_avg_s
     out = {
         "metric": "live spin-flip attempts/s (uneven batch)",
         "value": attempts * args.steps / wall,
@@ -332,17 +381,14 @@ def uneven(args):
                    "swap_interval": cfg["swap_interval"], "block_waves": bw,
                    "autotune_us_per_sweep": us, "live_attempts_per_sweep": live_per_sweep,
                    "live_fraction_of_lane_slots": live_per_sweep / lane_slots},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
-                     "unit": "Tops/s (int32 lane operations)", "frac": achieved / PEAK_INT32_OPS,
-                     "traffic": None, "kernel_ms_avg": float(np.mean(kernel_ms)),
-                     "ops_per_attempt": A_OPS},
+        "roofline": dict(alu_roofline(attempts, k_avg_s), traffic=None, kernel_ms_avg=float(np.mean(kernel_ms))),
         "energy_mismatches": mism,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = mixed_cpu_baseline(insts, cfg["seed"], cfg["swap_interval"], args.cpu_seconds)
     graph.close()
     batch.close()
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def _write_decisions(args, arm, run, mode="a"):
@@ -423,7 +469,7 @@ def search(args):
         plain = S.SearchConfig(mode="plain", chains=args.search_chains)
         out["cpu_baseline"] = search_cpu_baseline(plain, seeds, args.cpu_seconds,
                                                   arms["plain"]["pt_sweeps"] / args.search_steps)
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def search_reverse(args):
@@ -465,7 +511,7 @@ def search_reverse(args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = search_cpu_baseline(cfg, seeds, args.cpu_seconds,
                                                   run.pt_sweeps / args.search_steps, "reversed search step")
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def tau(args):
@@ -532,7 +578,7 @@ def tau(args):
         per_inst = c["per_emcs"] * T + c["acf"]
         out["cpu_baseline"] = {"value": c["cores"] * 3600.0 / per_inst, "unit": out["unit"], "cores": c["cores"],
                                "kind": "oracle", "sample": c["sample"]}
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def lao(args):
@@ -575,7 +621,7 @@ def lao(args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = search_cpu_baseline(cfg, [i["J"] for i in run.inst], args.cpu_seconds,
                                                   (run.pt_sweeps - sweeps0) / args.search_steps, "LAO step")
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def overlap(args):
@@ -665,7 +711,7 @@ def overlap(args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = overlap_cpu_baseline(insts, K, R, beta, si, T, max_lag, n_snap,
                                                    float(np.mean(analysed)) if analysed else 0.0, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 def overlap_cpu_baseline(insts, K, R, beta, si, T, max_lag, n_snap, n_analysed, budget_s):
@@ -739,7 +785,7 @@ def surrogate(args):
                         "kernel_ms_avg": out["train"]["ms"]}}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = surrogate_cpu_baseline(n_par, L, args.cpu_seconds)
-    print(json.dumps(res), flush=True)
+    emit(res)
 
 
 def surrogate_cpu_baseline(n_par, L, budget_s):
@@ -832,7 +878,10 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = attempts_per_step * args.steps / wall
     k_avg_s = float(np.mean(kernel_ms)) / 1e3
-    achieved = attempts_per_step * A_OPS / k_avg_s
+    roof = alu_roofline(attempts_per_step, k_avg_s)
+    roof.update({"traffic": measured_traffic(), "kernel_ms_avg": float(np.mean(kernel_ms)),
+                 "kernel": "hs::dev::k_pt_sweep", "kernel_fingerprint": kernel_fingerprint(),
+                 "issue_rates_measured_lane_ops_per_s": measured_issue_rates()})
     out = {
         "metric": "spin-flip attempts/s (C8 PT batch)",
         "value": value,
@@ -849,12 +898,7 @@ def main():
         "config": {"workload": cfg["name"], "instances": n_inst, "L": cfg["L"], "N": n_sites,
                    "couplers": 1472, "K": cfg["K"], "R": cfg["R"], "sweeps_per_step": sweeps,
                    "swap_interval": cfg["swap_interval"], "alphabet": "+-1..+-7"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
-                     "unit": "Tops/s (int32 lane operations)",
-                     "frac": achieved / PEAK_INT32_OPS, "traffic": measured_traffic(),
-                     "kernel_ms_avg": float(np.mean(kernel_ms)),
-                     "ops_per_attempt": A_OPS,
-                     "kernel_fingerprint": kernel_fingerprint()},
+        "roofline": roof,
         "energy_mismatches": mism,
     }
     if args.probe:
@@ -862,7 +906,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, insts, args.cpu_seconds)
     batch.close()
-    print(json.dumps(out), flush=True)
+    emit(out)
 
 
 if __name__ == "__main__":

@@ -47,3 +47,28 @@ def test_products_count_of_the_autocorrelation_sums():
     # sum over d = 0..M of (T - d), and lags beyond the run are empty
     assert bench._products(10, 3) == 10 + 9 + 8 + 7
     assert bench._products(4, 100) == 4 + 3 + 2 + 1
+
+
+def test_roofline_uses_the_committed_reference_op_count():
+    """frac is reported at the reference op count fixed before tuning (22
+    int32 lane operations per attempt, whose parts add up), with the
+    implemented formulation's count (15.5) beside it, against the peak
+    derived from the published fp32 vector figure."""
+    sys.path.insert(0, ROOT)
+    import bench
+    with open(os.path.join(ROOT, "roofline_opcount.json")) as f:
+        oc = json.load(f)
+    for part in ("reference", "implemented"):
+        assert sum(v["ops"] for v in oc[part]["parts"].values()) == oc[part]["ops_per_attempt"]
+    assert bench.A_OPS == 22 and bench.A_OPS_IMPL == 15.5
+    assert bench.PEAK_INT32_OPS == pytest.approx(157.3e12 / 2, rel=1e-3)
+    r = bench.alu_roofline(1.46e12 * 0.5, 0.5)
+    assert r["frac"] == pytest.approx(1.46e12 * 22 / bench.PEAK_INT32_OPS)
+    assert r["frac_implemented_ops"] == pytest.approx(1.46e12 * 15.5 / bench.PEAK_INT32_OPS)
+
+
+def test_cpu_baseline_records_the_host():
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.host_info()
+    assert h["host_nproc"] >= 1 and h["thread_cap"] == 16 and "16" in h["thread_cap_reason"]
