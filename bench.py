@@ -408,6 +408,12 @@ def _search_progress(name, args):
     return report
 
 
+# The time-to-solution every search line reports, next to its numbers.
+TTS_READING = ("ln TTS = ln(sweeps of all restarts / restarts whose minimum is the ground-state energy), the run time "
+               "per find of the ground state after Appendix B, in sweeps; not the median over restarts that the "
+               "workload description names")
+
+
 def search(args):
     """Hard instances per hour of the instance search (Algorithm 1) on C8:
     plain chains, surrogate-screened chains and the random-screen ablation,
@@ -432,22 +438,35 @@ def search(args):
         hours = wall / 3600.0
         hard = {name: len(run.hard.get(b, set())) for name, b in bars.items()}
         _write_decisions(args, mode, run, "w" if mode == "plain" else "a")
+        print(f"# {mode}: validating {len(run.hard_J)} counted states", file=sys.stderr, flush=True)
+        val = S.validate(run, seeds, tuple(bars.values()))
+        v_hours = (wall + val["seconds"]) / 3600.0
         finite = np.isfinite(run.ln)
         arms[mode] = {
             "steps": args.search_steps, "seconds": wall, "s_per_step": wall / args.search_steps,
             "init_seconds": t_init, "pt_seconds": run.pt_seconds, "gnn_seconds": run.gnn_seconds,
             "pt_sweeps": int(run.pt_sweeps), "accepted": run.accepted, "h0_ln_tts": run.h0,
             "pt_device_ms": run.pt_device_ms, "pt_attempts": int(run.pt_attempts), "pt_calls": run.pt_calls,
+            "validated_hard_instances": {name: val["counts"][b] for name, b in bars.items()},
+            "validated_hard_instances_per_hour": {name: val["counts"][b] / v_hours for name, b in bars.items()},
+            "validation": {"h0_fresh_ln_tts": val["h0"], "states": val["states"], "restarts": val["restarts"],
+                           "seconds": val["seconds"], "pt_sweeps": val["sweeps"],
+                           "rule": "a counted state is re-scored with 64 restarts on streams disjoint from the "
+                                   "search's and kept if its fresh ln TTS >= H0' + bar (H0' = median fresh ln TTS "
+                                   "of the seeds) and its ground state is confirmed; the hour includes this "
+                                   "re-scoring"},
             "hard_instances": hard,
             "hard_instances_per_hour": {k: v / hours for k, v in hard.items()},
             "final_median_ln_tts_finite": float(np.median(run.ln[finite])) if finite.any() else None,
             "final_censored_chains": int((~finite).sum()),
         }
-    rate = lambda m: arms[m]["hard_instances_per_hour"]["ln10"]
+    rate = lambda m: arms[m]["validated_hard_instances_per_hour"]["ln10"]
+    raw = lambda m: arms[m]["hard_instances_per_hour"]["ln10"]
     out = {
         "metric": "hard instances/hour, surrogate vs plain",
         "value": rate("surrogate"),
-        "unit": "hard instances/hour (ln TTS >= H0 + ln 10)",
+        "unit": "validated hard instances/hour (fresh ln TTS >= H0' + ln 10)",
+        "tts_reading": TTS_READING,
         "n_gpus": 1, "steps": args.search_steps, "warmup": 0,
         "ms_per_step": arms["surrogate"]["s_per_step"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -457,6 +476,8 @@ def search(args):
                    "bounded_steps": args.search_steps, "chain_groups": args.search_groups,
                    "screen": f"16 proposals, top {args.search_top} scored by PT"},
         "surrogate_over_plain": (rate("surrogate") / rate("plain")) if rate("plain") > 0 else None,
+        "surrogate_over_plain_unvalidated": (raw("surrogate") / raw("plain")) if raw("plain") > 0 else None,
+        "random_over_plain": (rate("random") / rate("plain")) if rate("plain") > 0 else None,
         "arms": arms,
         "roofline": pt_roofline(sum(a["pt_attempts"] for a in arms.values()),
                                 sum(a["pt_device_ms"] for a in arms.values()),
@@ -490,11 +511,18 @@ def search_reverse(args):
     wall = time.perf_counter() - t0
     easy = {name: len(run.hard.get(b, set())) for name, b in bars.items()}
     _write_decisions(args, "reverse", run, "w")
+    val = S.validate(run, seeds, tuple(bars.values()))
+    v_easy = {name: val["counts"][b] for name, b in bars.items()}
     med = float(np.median(run.ln))
     out = {
         "metric": "easy instances/hour (reversed search)",
-        "value": easy["ln3"] / (wall / 3600.0),
-        "unit": "easy instances/hour (ln TTS <= H0 - ln 3)",
+        "value": v_easy["ln3"] / ((wall + val["seconds"]) / 3600.0),
+        "unit": "validated easy instances/hour (fresh ln TTS <= H0' - ln 3)",
+        "tts_reading": TTS_READING,
+        "unvalidated_easy_instances_per_hour": easy["ln3"] / (wall / 3600.0),
+        "validated_easy_instances": v_easy,
+        "validation": {"h0_fresh_ln_tts": val["h0"], "states": val["states"], "restarts": val["restarts"],
+                       "seconds": val["seconds"]},
         "n_gpus": 1, "steps": args.search_steps, "warmup": 0,
         "ms_per_step": wall * 1e3 / args.search_steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

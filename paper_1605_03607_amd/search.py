@@ -141,6 +141,7 @@ class Search:
         self.h0 = float(np.median(self.ln)) if h0 is None else float(h0)
         self.accepted = 0
         self.hard = {}
+        self.hard_J = {}  # couplings of every counted state, by key
         self.decisions = []
 
     @property
@@ -248,7 +249,9 @@ class Search:
                 self.accepted += 1
                 for b in bars:
                     if d * (y - self.h0) >= b:
-                        self.hard.setdefault(b, set()).add(_key(J2))
+                        k = _key(J2)
+                        self.hard.setdefault(b, set()).add(k)
+                        self.hard_J.setdefault(k, J2)
         self._train()
         self.step += 1
 
@@ -364,6 +367,13 @@ class GroupedSearch:
         return out
 
     @property
+    def hard_J(self):
+        out = {}
+        for g in self.groups:
+            out.update(g.hard_J)
+        return out
+
+    @property
     def accepted(self):
         return sum(g.accepted for g in self.groups)
 
@@ -390,6 +400,57 @@ class GroupedSearch:
     @property
     def gnn_seconds(self):
         return self.pool.gnn_seconds
+
+
+# ---------------------------------------------------------------------------
+# Validation of counted states.  The search scores every candidate of a chain
+# with the same restart streams (instance_id = the chain's index), a common
+# random number choice that makes decisions reproducible and compares
+# proposals on equal terms; but a state can then look hard only because these
+# streams are slow on it.  Appendix B re-measures a final instance with many
+# independent runs: here every counted state, and every seed instance (for
+# H0), is scored again with VALIDATION_RESTARTS restarts whose Philox keys
+# carry a second word (seed XOR VALIDATION_SEED_XOR) that no search stream
+# uses, so the validation streams are disjoint from the search's.
+
+VALIDATION_SEED_XOR = 0x7A11DA7E
+VALIDATION_RESTARTS = 64
+
+
+def validation_seed(cfg):
+    return (int(cfg.seed) ^ VALIDATION_SEED_XOR) & 0xFFFFFFFF
+
+
+def validate(run, seeds, bars, restarts=VALIDATION_RESTARTS, chunk=256):
+    """Re-scores the seed instances and every counted state of `run` (a
+    Search or GroupedSearch) with independent restart streams.  A state is
+    validated at bar b when its fresh ln TTS clears H0' + b (H0' = median
+    fresh ln TTS of the seeds; below H0' - b for the reversed search) and its
+    ground state is confirmed.  Returns a dict with H0', the validated counts
+    per bar, the fresh scores and the seconds spent."""
+    c = run.cfg
+    states = run.hard_J
+    keys = sorted(states)
+    cands = [dict(L=c.L, J=np.asarray(J, np.int8), live=None, instance_id=i) for i, J in enumerate(seeds)]
+    cands += [dict(L=c.L, J=states[k], live=None, instance_id=len(seeds) + i) for i, k in enumerate(keys)]
+    seed_v = validation_seed(c)
+    t0 = time.perf_counter()
+    ln, conf, sweeps = [], [], 0
+    for a in range(0, len(cands), chunk):
+        part = cands[a:a + chunk]
+        y, det = hardness_eval(part, restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, seed_v)
+        ln += [float(v) for v in y]
+        conf += [bool(dd["confirmed"]) for dd in det]
+        sweeps += sum(int(dd["sweeps_total"]) for dd in det)
+    seconds = time.perf_counter() - t0
+    h0v = float(np.median(ln[:len(seeds)]))
+    fresh = {k: (ln[len(seeds) + i], conf[len(seeds) + i]) for i, k in enumerate(keys)}
+    d = c.direction
+    counts = {}
+    for b in bars:
+        counts[b] = sum(1 for k in keys if fresh[k][1] and d * (fresh[k][0] - h0v) >= b)
+    return dict(h0=h0v, counts=counts, fresh=fresh, seconds=seconds, sweeps=sweeps, restarts=restarts,
+                seed=seed_v, states=len(keys))
 
 
 class LaoSearch:
@@ -528,7 +589,7 @@ class GroupedLao:
 # objects, written to a temporary name and renamed, so a process killed while
 # saving leaves the previous checkpoint intact.
 
-_CKPT_VERSION = 1
+_CKPT_VERSION = 2
 _CFG_KEYS = ("mode", "direction", "chains", "L", "restarts", "K", "R", "swap_interval", "s_max", "t_s", "seed",
              "proposals", "top", "train_steps", "train_batch", "lr", "replay")
 
@@ -560,7 +621,6 @@ def save_search(run, path):
             "hard": {b: sorted(k) for b, k in hard.items()},
             "rng": pool.rng.bit_generator.state, "sur_step": pool.sur.step if pool.sur is not None else 0}
     arrays = {
-        "meta": np.frombuffer(json.dumps(meta).encode(), np.uint8),
         "ids": np.array([i for g in groups for i in g.ids], np.int64),
         "J": np.stack([J for g in groups for J in g.J]).astype(np.int8),
         "ln": np.concatenate([g.ln for g in groups]).astype(np.float64),
@@ -569,10 +629,18 @@ def save_search(run, path):
                     else np.zeros((0, len(groups[0].J[0])), np.int8)),
         "pairs_y": np.array(pool.pairs_y, np.float64),
     }
+    hard_J = {}
+    for g in groups:
+        hard_J.update(g.hard_J)
+    hk = sorted(hard_J)
+    meta["hard_J_keys"] = hk
+    arrays["hard_J"] = (np.stack([hard_J[k] for k in hk]).astype(np.int8) if hk
+                        else np.zeros((0, len(groups[0].J[0])), np.int8))
     if pool.sur is not None:
         arrays["sur_params"] = pool.sur.params.cpu().numpy()
         arrays["sur_m"] = pool.sur.m.cpu().numpy()
         arrays["sur_v"] = pool.sur.v.cpu().numpy()
+    arrays["meta"] = np.frombuffer(json.dumps(meta).encode(), np.uint8)
     tmp = path + ".tmp.npz"
     np.savez(tmp, **arrays)
     os.replace(tmp, path)
@@ -615,6 +683,7 @@ def load_search(path, cfg, groups=1):
         owner[d[1]].decisions.append(d)
     parts[0].accepted = int(meta["accepted"])
     parts[0].hard = {float(b): set(keys) for b, keys in meta["hard"].items()}
+    parts[0].hard_J = {k: a["hard_J"][i].copy() for i, k in enumerate(meta["hard_J_keys"])}
     if groups == 1:
         return parts[0]
     run = GroupedSearch.__new__(GroupedSearch)

@@ -210,3 +210,57 @@ def test_checkpoint_needs_groups_at_one_step(S, tmp_path):
     run.groups[1].run_step()
     with pytest.raises(ValueError, match="different steps"):
         S.save_search(run, str(tmp_path / "x.npz"))
+
+
+def test_validation_uses_restart_streams_disjoint_from_the_search(S, monkeypatch):
+    """Counted states and the seed instances are re-scored with 64 restarts
+    whose Philox keys (restart key, seed') all have seed' != the search's
+    seed, so no validation stream is one the search used (every search key
+    is (restart key, seed)); the validated counts come from those fresh
+    scores, against the median fresh score of the seeds."""
+    calls = []
+
+    def recording(cands, n_restarts, K, R, beta, swap_interval, s_max, seed):
+        calls.append((seed, n_restarts, len(cands)))
+        return _fake_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed)
+
+    monkeypatch.setattr(S, "hardness_eval", recording)
+    cfg = S.SearchConfig(mode="plain", chains=6, L=2, t_s=5.0)
+    seeds = [workloads.couplings(2, "pm1", 47, c) for c in range(6)]
+    run = S.GroupedSearch(cfg, seeds, groups=2)
+    bars = (math.log(1.1), math.log(1.5))
+    run.run(6, bars=bars)
+    search_seeds = {sd for sd, _, _ in calls}
+    assert search_seeds == {cfg.seed}
+    n_calls = len(calls)
+    assert run.hard_J and set(run.hard_J) == run.hard[bars[0]] | run.hard.get(bars[1], set())
+    v = S.validate(run, seeds, bars)
+    fresh_calls = calls[n_calls:]
+    assert fresh_calls and all(sd == S.validation_seed(cfg) != cfg.seed and nr == 64 for sd, nr, _ in fresh_calls)
+    assert sum(n for _, _, n in fresh_calls) == len(seeds) + len(run.hard_J)
+    # the fake scorer depends on the instance id, as PT's ln TTS depends on
+    # the restart streams: recompute the validated counts from its values
+    fresh = [_fake_eval([dict(J=s, instance_id=i)], 0, 0, 0, 0, 0, 0, 0)[0][0] for i, s in enumerate(seeds)]
+    h0v = float(np.median(fresh))
+    assert v["h0"] == h0v
+    keys = sorted(run.hard_J)
+    for b in bars:
+        want = 0
+        for i, k in enumerate(keys):
+            y = _fake_eval([dict(J=run.hard_J[k], instance_id=len(seeds) + i)], 0, 0, 0, 0, 0, 0, 0)[0][0]
+            want += int(y - h0v >= b)
+        assert v["counts"][b] == want
+
+
+def test_checkpoint_keeps_the_counted_couplings(S, tmp_path):
+    cfg = S.SearchConfig(mode="plain", chains=4, L=2, t_s=5.0)
+    seeds = [workloads.couplings(2, "pm1", 49, c) for c in range(4)]
+    run = S.Search(cfg, seeds)
+    for _ in range(4):
+        run.run_step(bars=(math.log(1.1),))
+    assert run.hard_J
+    path = str(tmp_path / "ck.npz")
+    S.save_search(run, path)
+    back = S.load_search(path, cfg)
+    assert sorted(back.hard_J) == sorted(run.hard_J)
+    assert all(np.array_equal(back.hard_J[k], run.hard_J[k]) for k in run.hard_J)
