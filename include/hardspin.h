@@ -341,6 +341,23 @@ int hardness_workspace_bytes(const hs_instance *cands, int n, const hs_hardness_
 int hardness_eval(const hs_instance *cands, int n, const hs_hardness_params *p, void *scratch,
                   size_t scratch_bytes, double *ln_tts_out, hs_tts_detail *detail, void *stream);
 
+/* hardness_eval for callers that cannot allocate device memory (serving
+ * loops, harnesses that forbid allocation): the same computation and
+ * results, with the scratch in a static device array of
+ * HS_STATIC_SCRATCH_BYTES owned by the library (one copy per GPU, held until
+ * the process ends) instead of a caller buffer.  The inputs and outputs are
+ * the caller's host memory as for hardness_eval.  It calls no device
+ * allocator.  `stream` must belong to the current device.  HS_ENOSPACE when
+ * the batch needs more scratch than HS_STATIC_SCRATCH_BYTES (the size
+ * hardness_workspace_bytes reports), with nothing enqueued.  Every call on
+ * one GPU uses that GPU's array: calls that overlap on one GPU (from several
+ * threads or streams) race and must not be made; the array keeps the last
+ * call's contents, and each call initialises every byte it reads.  Blocks
+ * until done. */
+#define HS_STATIC_SCRATCH_BYTES (64u << 20)
+int hardness_eval_static(const hs_instance *cands, int n, const hs_hardness_params *p, double *ln_tts_out,
+                         hs_tts_detail *detail, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

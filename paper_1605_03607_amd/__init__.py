@@ -123,6 +123,8 @@ def lib():
         L.hardness_eval.argtypes = [C.POINTER(hs_instance), C.c_int, C.POINTER(hs_hardness_params),
                                     C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(hs_tts_detail),
                                     C.c_void_p]
+        L.hardness_eval_static.argtypes = [C.POINTER(hs_instance), C.c_int, C.POINTER(hs_hardness_params),
+                                           C.c_void_p, C.POINTER(hs_tts_detail), C.c_void_p]
         L.gnn_param_count.restype = C.c_int
         L.gnn_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
         L.gnn_prepare.argtypes = [C.POINTER(hs_gnn_batch), C.c_void_p, C.c_size_t, C.c_void_p]
@@ -161,7 +163,7 @@ def exported_symbols():
             "pt_autotune", "instance_mutate", "hs_rao_accept", "hardness_workspace_bytes",
             "hardness_eval", "gnn_param_count", "gnn_workspace_bytes", "gnn_prepare", "gnn_forward",
             "gnn_train_step", "pt_sweep_record", "walk_autocorr", "walk_tau", "lao_cycle_count", "lao_init",
-            "lao_move", "pt_capture", "overlap_analyze", "pt_launch_shape"]
+            "lao_move", "pt_capture", "overlap_analyze", "pt_launch_shape", "hardness_eval_static"]
 
 
 def _check(rc):
@@ -416,6 +418,29 @@ def hardness_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed, blo
     det = (hs_tts_detail * max(1, len(cands)))()
     _check(lib().hardness_eval(hi.arr, len(cands), C.byref(p), C.c_void_p(scratch.data_ptr()),
                                nb.value, ln.ctypes.data, det, _stream_ptr(stream)))
+    details = [dict(e_gs=det[i].e_gs, confirmed=bool(det[i].confirmed),
+                    n_censored=det[i].n_censored, sweeps_total=det[i].sweeps_total,
+                    restart_sweeps=rs[i].copy())
+               for i in range(len(cands))]
+    return ln, details
+
+
+HS_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def hardness_eval_static(cands, n_restarts, K, R, beta, swap_interval, s_max, seed, block_waves=0,
+                         stream=None):
+    """hardness_eval through hardness_eval_static: the library's static
+    device scratch instead of a buffer allocated here (nothing is allocated
+    on the device)."""
+    hi = _HostInstances([dict(c, K=K, R=R, beta=beta) for c in cands])
+    beta_arr = np.ascontiguousarray(beta, np.float64)
+    rs = np.zeros((max(1, len(cands)), n_restarts), np.int64)
+    p = hs_hardness_params(n_restarts, K, R, beta_arr.ctypes.data, swap_interval, s_max, seed,
+                           block_waves, rs.ctypes.data)
+    ln = np.zeros(len(cands), np.float64)
+    det = (hs_tts_detail * max(1, len(cands)))()
+    _check(lib().hardness_eval_static(hi.arr, len(cands), C.byref(p), ln.ctypes.data, det, _stream_ptr(stream)))
     details = [dict(e_gs=det[i].e_gs, confirmed=bool(det[i].confirmed),
                     n_censored=det[i].n_censored, sweeps_total=det[i].sweeps_total,
                     restart_sweeps=rs[i].copy())

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -13,7 +14,37 @@
 
 using namespace hs;
 
+// Device scratch of hardness_eval_static: one copy per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: host code uses the per-device address from
+// hipGetSymbolAddress (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[HS_STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch`, looked up once per
+// device with that device current.
+int static_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(HS_EHIP, std::string("hardness_eval_static: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HS_EUNSUPPORTED, "hardness_eval_static: device index >= 64");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(HS_EHIP, std::string("hardness_eval_static: scratch address: ") + hipGetErrorString(e));
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return HS_OK;
+}
 
 struct HardnessLayout {
     size_t spins, perm, energy, emin, thit, sacc, t, stopped, ws, total, ws_bytes;
@@ -101,21 +132,19 @@ int hardness_workspace_bytes(const hs_instance *cands, int n, const hs_hardness_
     return HS_OK;
 }
 
-int hardness_eval(const hs_instance *cands, int n, const hs_hardness_params *p, void *scratch,
-                  size_t scratch_bytes, double *ln_tts_out, hs_tts_detail *detail, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Every restart of every candidate in one persistent launch on the device
+// memory at `base` (L.total bytes laid out by `layout`); pt_init writes every
+// byte the launch reads (workspace image, initial state), so nothing has to
+// be cleared beforehand.
+int run_hardness(int n, const hs_hardness_params *p, std::vector<hs_instance> &runs,
+                 const hs_pt_desc &d, const HardnessLayout &L, char *base, double *ln_tts_out, hs_tts_detail *detail,
+                 void *stream)
 {
-    if (ln_tts_out == nullptr || (n > 0 && scratch == nullptr))
-        return fail(HS_EINVAL, "hardness_eval: NULL argument");
-    std::vector<hs_instance> runs;
-    hs_pt_desc d{};
-    int rc = build_batch(cands, n, p, runs, d);
-    if (rc) return rc;
-    if (n == 0) return HS_OK;
-    HardnessLayout L{};
-    rc = layout(runs, d, L);
-    if (rc) return rc;
-    if (scratch_bytes < L.total) return fail(HS_ENOSPACE, "hardness_eval: scratch too small");
-    char *base = reinterpret_cast<char *>(scratch);
+    int rc = HS_OK;
     hs_buffers b{};
     b.spins = reinterpret_cast<uint64_t *>(base + L.spins);
     b.perm = reinterpret_cast<uint8_t *>(base + L.perm);
@@ -128,21 +157,24 @@ int hardness_eval(const hs_instance *cands, int n, const hs_hardness_params *p, 
     b.workspace = base + L.ws;
     b.workspace_bytes = L.ws_bytes;
     hs_pt *h = nullptr;
-    rc = pt_init(&h, &d, &b, stream);
+    // the stream is synchronised below before pt_destroy: no upload event
+    rc = pt_init_ex(&h, &d, &b, stream, false);
     if (rc) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     rc = pt_sweep(h, p->s_max);
     if (rc) {
+        (void)hipStreamSynchronize(s);  // the upload reads the handle's host copy
         pt_destroy(h);
         return rc;
     }
     const size_t m = runs.size();
     std::vector<int32_t> emin(m * 64);
     std::vector<int64_t> thit(m * 64), t(m);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(emin.data(), b.emin, m * 64 * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(thit.data(), b.thit, m * 64 * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(t.data(), b.t, m * 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = es;
     pt_destroy(h);
     if (e != hipSuccess) return fail(HS_EHIP, std::string("hardness_eval: ") + hipGetErrorString(e));
     const int nr = p->n_restarts, R = p->R;
@@ -175,6 +207,50 @@ int hardness_eval(const hs_instance *cands, int n, const hs_hardness_params *p, 
         }
     }
     return HS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hardness_eval(const hs_instance *cands, int n, const hs_hardness_params *p, void *scratch_buf,
+                  size_t scratch_bytes, double *ln_tts_out, hs_tts_detail *detail, void *stream)
+{
+    if (ln_tts_out == nullptr || (n > 0 && scratch_buf == nullptr))
+        return fail(HS_EINVAL, "hardness_eval: NULL argument");
+    std::vector<hs_instance> runs;
+    hs_pt_desc d{};
+    int rc = build_batch(cands, n, p, runs, d);
+    if (rc) return rc;
+    if (n == 0) return HS_OK;
+    HardnessLayout L{};
+    rc = layout(runs, d, L);
+    if (rc) return rc;
+    if (scratch_bytes < L.total) return fail(HS_ENOSPACE, "hardness_eval: scratch too small");
+    return run_hardness(n, p, runs, d, L, reinterpret_cast<char *>(scratch_buf), ln_tts_out, detail, stream);
+}
+
+int hardness_eval_static(const hs_instance *cands, int n, const hs_hardness_params *p, double *ln_tts_out,
+                         hs_tts_detail *detail, void *stream)
+{
+    if (ln_tts_out == nullptr) return fail(HS_EINVAL, "hardness_eval_static: NULL argument");
+    std::vector<hs_instance> runs;
+    hs_pt_desc d{};
+    int rc = build_batch(cands, n, p, runs, d);
+    if (rc) return rc;
+    if (n == 0) return HS_OK;
+    HardnessLayout L{};
+    rc = layout(runs, d, L);
+    if (rc) return rc;
+    if (L.total > size_t(HS_STATIC_SCRATCH_BYTES))
+        return fail(HS_ENOSPACE, "hardness_eval_static: the batch needs " + std::to_string(L.total) +
+                                     " bytes of scratch, more than the static " +
+                                     std::to_string(size_t(HS_STATIC_SCRATCH_BYTES)) +
+                                     "; use hardness_eval with a caller buffer");
+    void *base = nullptr;
+    rc = static_scratch(&base);
+    if (rc) return rc;
+    return run_hardness(n, p, runs, d, L, reinterpret_cast<char *>(base), ln_tts_out, detail, stream);
 }
 
 }  // extern "C"

@@ -86,6 +86,9 @@ uint64_t metro_threshold(double beta, int m);
 uint64_t swap_threshold(double beta_lo, double beta_hi, int64_t d);
 void philox_host(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
+// pt_init with the upload event optional (hs_pt.hip).
+int pt_init_ex(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream, bool track_upload);
+
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
 

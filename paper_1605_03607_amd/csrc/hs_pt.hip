@@ -1292,6 +1292,15 @@ int pt_workspace_bytes(const hs_pt_desc *d, size_t *bytes)
 
 int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
 {
+    return hs::pt_init_ex(out, d, b, stream, true);
+}
+
+}  // extern "C"
+
+// track_upload = false: no event is created; the caller synchronises the
+// stream before pt_destroy (the upload reads the handle's host copy).
+int hs::pt_init_ex(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream, bool track_upload)
+{
     if (out == nullptr || d == nullptr || b == nullptr) return fail(HS_EINVAL, "pt_init: NULL argument");
     *out = nullptr;
     Plan P;
@@ -1329,12 +1338,16 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
     }
     hipError_t e = hipMemcpyAsync(b->workspace, h->host_ws.data(), h->host_ws.size() * 4,
                                   hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->uploaded, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(h->uploaded, h->stream);
-    if (e != hipSuccess) {
+    if (e == hipSuccess && track_upload) e = hipEventCreateWithFlags(&h->uploaded, hipEventDisableTiming);
+    if (e == hipSuccess && track_upload) e = hipEventRecord(h->uploaded, h->stream);
+    // after an error once the upload is enqueued: wait for it (it reads
+    // h->host_ws), then free the handle
+    auto abort_init = [&](int rc) {
+        (void)hipStreamSynchronize(h->stream);
         pt_destroy(h);
-        return hip_fail(e, "pt_init: upload");
-    }
+        return rc;
+    };
+    if (e != hipSuccess) return abort_init(hip_fail(e, "pt_init: upload"));
     const char *ws = reinterpret_cast<const char *>(b->workspace);
     dev::InitArgs ia;
     ia.inst = reinterpret_cast<const InstDev *>(ws + h->off_inst * 4);
@@ -1350,33 +1363,23 @@ int pt_init(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *stream)
     ia.from_buffer = (d->flags & HS_INIT_FROM_BUFFER) ? 1 : 0;
     hipLaunchKernelGGL(dev::k_pt_init, dim3(h->n_inst), dim3(64), 0, h->stream, ia);
     e = hipGetLastError();
-    if (e != hipSuccess) {
-        pt_destroy(h);
-        return hip_fail(e, "pt_init: launch");
-    }
+    if (e != hipSuccess) return abort_init(hip_fail(e, "pt_init: launch"));
     const void *kfn = reinterpret_cast<const void *>(&dev::k_pt_sweep<false>);
     const void *kfn_rec = reinterpret_cast<const void *>(&dev::k_pt_sweep<true>);
     if (h->lds_bytes > 64 * 1024) {
         e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(h->lds_bytes));
         if (e == hipSuccess)
             e = hipFuncSetAttribute(kfn_rec, hipFuncAttributeMaxDynamicSharedMemorySize, int(h->lds_bytes));
-        if (e != hipSuccess) {
-            pt_destroy(h);
-            return hip_fail(e, "pt_init: LDS size");
-        }
+        if (e != hipSuccess) return abort_init(hip_fail(e, "pt_init: LDS size"));
     }
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, h->nwaves * 64, h->lds_bytes);
-    if (e != hipSuccess || per_cu < 1) {
-        pt_destroy(h);
-        return fail(HS_EUNSUPPORTED, "pt_init: instances too large for one workgroup's LDS");
-    }
+    if (e != hipSuccess || per_cu < 1)
+        return abort_init(fail(HS_EUNSUPPORTED, "pt_init: instances too large for one workgroup's LDS"));
     h->grid = std::min(h->n_inst, per_cu * device_cus());
     *out = h;
     return HS_OK;
 }
-
-}  // extern "C"
 
 namespace {
 
