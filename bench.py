@@ -85,6 +85,8 @@ def parse():
                    help="c8: the 256 x C8 batch (default); uneven: 1024 instances C4..C12, "
                         "autotuned shape, HIP-graph replay, live attempts/s; search: bounded "
                         "plain / surrogate-screened / random-screened instance search")
+    p.add_argument("--pack", choices=["auto", "on", "off"], default="auto",
+                   help="uneven workload: lane packing of instances of one size (auto: the tuner decides)")
     p.add_argument("--search-steps", type=int, default=20)
     p.add_argument("--search-chains", type=int, default=64)
     p.add_argument("--search-groups", type=int, default=4,
@@ -344,13 +346,23 @@ def uneven(args):
     insts = cfg["instances"]
     sweeps = args.sweeps or cfg["sweeps"]
     live_per_sweep = sum(int(d["K"]) * int(d["R"]) * int(np.count_nonzero(d["live"])) for d in insts)
-    lane_slots = sum(64 * 8 * int(d["L"]) ** 2 for d in insts)
+    # the tuner times the workgroup shapes of the plain plan (one instance per
+    # workgroup) and of the packed plan (instances of one size sharing lanes)
+    plans = {"off": [0], "on": [hs.HS_PACK_LANES], "auto": [0, hs.HS_PACK_LANES]}[args.pack]
     t0 = time.perf_counter()
-    bw, us = (args.block_waves, None) if args.block_waves else hs.autotune(
-        insts, cfg["seed"], swap_interval=cfg["swap_interval"], trial_sweeps=200)
+    tried = []
+    for flags in plans:
+        if args.block_waves:
+            tried.append((0.0, args.block_waves, flags))
+        else:
+            bw_f, us_f = hs.autotune(insts, cfg["seed"], swap_interval=cfg["swap_interval"], flags=flags,
+                                     trial_sweeps=200)
+            tried.append((us_f, bw_f, flags))
+    us, bw, flags = min(tried)
     tune_s = time.perf_counter() - t0
-    print(f"# autotune: block_waves={bw} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
-    batch = hs.PTBatch(insts, cfg["seed"], swap_interval=cfg["swap_interval"], block_waves=bw)
+    print(f"# autotune: {tried} -> block_waves={bw}, flags={flags} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
+    batch = hs.PTBatch(insts, cfg["seed"], swap_interval=cfg["swap_interval"], block_waves=bw, flags=flags)
+    _, _, _, items, lane_slots = batch.launch_shape()
     graph = batch.graph(sweeps)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -379,7 +391,11 @@ def uneven(args):
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": cfg["name"], "instances": len(insts), "sweeps_per_step": sweeps,
                    "swap_interval": cfg["swap_interval"], "block_waves": bw,
-                   "autotune_us_per_sweep": us, "live_attempts_per_sweep": live_per_sweep,
+                   "packed_lanes": bool(flags & hs.HS_PACK_LANES), "work_items": items,
+                   "autotune_us_per_sweep": us,
+                   "autotune_tried": [{"us_per_sweep": t[0], "block_waves": t[1],
+                                       "packed_lanes": bool(t[2] & hs.HS_PACK_LANES)} for t in tried],
+                   "live_attempts_per_sweep": live_per_sweep,
                    "live_fraction_of_lane_slots": live_per_sweep / lane_slots},
         "roofline": dict(alu_roofline(attempts, k_avg_s), traffic=None, kernel_ms_avg=float(np.mean(kernel_ms))),
         "energy_mismatches": mism,

@@ -62,6 +62,8 @@ extern "C" {
 /* Flags of hs_pt_desc.flags */
 #define HS_INIT_FROM_BUFFER 1u   /* pt_init reads initial spins from buffers->spins */
 #define HS_STOP_ON_AGREEMENT 2u  /* stop an instance once all replica sets agree (see pt_sweep) */
+#define HS_PACK_LANES 4u         /* share a workgroup's 64 lanes between instances of one lattice size
+                                    (see hs_pt_desc); not with HS_STOP_ON_AGREEMENT */
 
 /* One problem instance and its temperature ladder.  Host memory; read during
  * the call only.
@@ -83,13 +85,19 @@ typedef struct hs_instance {
     const double *beta;
 } hs_instance;
 
-/* A batch of instances simulated together in one persistent launch. */
+/* A batch of instances simulated together in one persistent launch.
+ * With HS_PACK_LANES the launch plan packs instances of the same lattice size
+ * whose lane counts K R add up to at most 64 into one workgroup (two per
+ * workgroup at most), so that the lanes one instance leaves idle serve
+ * another.  Every instance keeps its own couplings, ladder, Philox key,
+ * replica sets and exchange passes: results are those of the unpacked launch
+ * (and of the oracle), only the lane occupancy changes. */
 typedef struct hs_pt_desc {
     int32_t n_inst;
     const hs_instance *inst; /* host array of n_inst */
     uint32_t seed;           /* second word of every Philox key */
     int32_t swap_interval;   /* exchange pass after every swap_interval-th sweep; 0 = none */
-    uint32_t flags;          /* HS_INIT_FROM_BUFFER | HS_STOP_ON_AGREEMENT */
+    uint32_t flags;          /* HS_INIT_FROM_BUFFER | HS_STOP_ON_AGREEMENT | HS_PACK_LANES */
     int32_t block_waves;     /* wavefronts per instance (1..16); 0 = one per cell pair of the
                                 largest instance, rounded up to a power of two, at most 16
                                 (pt_autotune measures the candidates instead) */
@@ -199,10 +207,15 @@ int pt_measure(hs_pt *h, int32_t *recomputed, int32_t *n_mismatch);
 int pt_destroy(hs_pt *h);
 
 /* Launch shape of the handle's persistent sweep kernel: workgroups in the
- * grid (at most n_inst; each takes instances from the work queue until it is
- * empty), wavefronts per workgroup and dynamic LDS bytes per workgroup.  Any
+ * grid (at most the work items; each takes items from the work queue until
+ * it is empty), wavefronts per workgroup, dynamic LDS bytes per workgroup,
+ * and the work items (n_inst, or the number of packs when HS_PACK_LANES
+ * packed the batch; equal to n_inst when nothing could be packed), and the
+ * lane slots one sweep passes through (sum over work items of 64 x the
+ * item's sites, live or not: the denominator of lane occupancy).  Any
  * output pointer may be NULL.  Host only. */
-int pt_launch_shape(const hs_pt *h, int32_t *grid, int32_t *block_waves, int32_t *lds_bytes);
+int pt_launch_shape(const hs_pt *h, int32_t *grid, int32_t *block_waves, int32_t *lds_bytes, int32_t *work_items,
+                    int64_t *lane_sites);
 
 /* One RAO move (Algorithm 1, Sec. II.A) as a pure host function.
  * (w0, w1, w2, w3) = Philox((chain, seed), (step, proposal, 0, 4)); the

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libhardspin.so")
 
 HS_INIT_FROM_BUFFER = 1
 HS_STOP_ON_AGREEMENT = 2
+HS_PACK_LANES = 4
 
 _ERRORS = {-1: "HS_EINVAL", -2: "HS_ENOSPACE", -3: "HS_EUNSUPPORTED", -4: "HS_EHIP",
            -5: "HS_EMISMATCH"}
@@ -108,7 +109,7 @@ def lib():
         L.pt_measure.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]
         L.pt_destroy.argtypes = [C.c_void_p]
         L.pt_launch_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                      C.POINTER(C.c_int32)]
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.pt_graph_create.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_void_p)]
         L.pt_graph_launch.argtypes = [C.c_void_p]
         L.pt_graph_destroy.argtypes = [C.c_void_p]
@@ -275,10 +276,11 @@ class PTBatch:
 
     def launch_shape(self):
         """(workgroups in the grid, wavefronts per workgroup, LDS bytes per
-        workgroup) of the persistent sweep launch."""
-        g, w, b = C.c_int32(0), C.c_int32(0), C.c_int32(0)
-        _check(lib().pt_launch_shape(self.h, C.byref(g), C.byref(w), C.byref(b)))
-        return g.value, w.value, b.value
+        workgroup, work items of the queue, lane slots per sweep) of the
+        persistent sweep launch."""
+        g, w, b, n, ls = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int64(0)
+        _check(lib().pt_launch_shape(self.h, C.byref(g), C.byref(w), C.byref(b), C.byref(n), C.byref(ls)))
+        return g.value, w.value, b.value, n.value, ls.value
 
     def measure(self):
         """Recomputes energies on the device; returns the mismatch count."""

@@ -150,21 +150,22 @@ int build_instance(const hs_instance &in, HostInstance &out, std::string &err)
 
 // Wavefront task table of an L x L lattice processed by nwaves wavefronts:
 // wavefront w, phase p, iteration i updates cell pair j = w + i nwaves
-// (cells 2j, 2j+1 in row-major order).  Entry (8 words): Philox counter word
+// (cells 2j, 2j+1 in row-major order).  Entry (16 words): Philox counter word
 // (j << 1 | p), quad indices q0 | q1 << 16 (q1 = 0xFFFF without a second
-// cell), then for each cell the spin rows own | opposite << 16 and
-// neighbour A | neighbour B << 16 (row 2 L^2 is the zero row).
+// cell), then for each cell the LDS byte offsets (row x 256) of the spin rows
+// own, opposite, neighbour A and neighbour B (row 2 L^2 is the zero row);
+// byte offsets, so the kernel adds them to its column address as they are.
 void build_tasks(int L, int nwaves, std::vector<uint32_t> &out, int &iters)
 {
     const int ncell = L * L, npairs = (ncell + 1) / 2, zero = 2 * ncell;
     iters = (npairs + nwaves - 1) / nwaves;
-    out.assign(size_t(nwaves) * 2 * iters * 8, 0u);
+    out.assign(size_t(nwaves) * 2 * iters * 16, 0u);
     for (int w = 0; w < nwaves; ++w)
         for (int p = 0; p < 2; ++p)
             for (int it = 0; it < iters; ++it) {
                 const int j = w + it * nwaves;
                 if (j >= npairs) continue;
-                uint32_t *e = &out[((size_t(w) * 2 + p) * iters + it) * 8];
+                uint32_t *e = &out[((size_t(w) * 2 + p) * iters + it) * 16];
                 e[0] = (uint32_t(j) << 1) | uint32_t(p);
                 uint32_t qs[2] = {0xFFFFu, 0xFFFFu};
                 for (int h = 0; h < 2; ++h) {
@@ -175,8 +176,10 @@ void build_tasks(int L, int nwaves, std::vector<uint32_t> &out, int &iters)
                     const int a = u == 0 ? (r > 0 ? (cell - L) * 2 : zero) : (c > 0 ? (cell - 1) * 2 + 1 : zero);
                     const int b = u == 0 ? (r + 1 < L ? (cell + L) * 2 : zero) : (c + 1 < L ? (cell + 1) * 2 + 1 : zero);
                     qs[h] = uint32_t(own);
-                    e[2 + 2 * h] = uint32_t(own) | (uint32_t(oth) << 16);
-                    e[3 + 2 * h] = uint32_t(a) | (uint32_t(b) << 16);
+                    e[2 + 4 * h] = uint32_t(own) * 256u;
+                    e[3 + 4 * h] = uint32_t(oth) * 256u;
+                    e[4 + 4 * h] = uint32_t(a) * 256u;
+                    e[5 + 4 * h] = uint32_t(b) * 256u;
                 }
                 e[1] = qs[0] | (qs[1] << 16);
             }

@@ -43,6 +43,21 @@ struct alignas(16) InstDev {
     int32_t pad_;
 };
 
+// Instances sharing one workgroup's 64 lanes (HS_PACK_LANES): member m holds
+// lanes lane0[m] .. lane0[m] + nlanes(m) - 1; its replica sets are segments
+// of K consecutive lanes.  An unpacked launch has one member per pack.
+constexpr int kMaxPack = 2;
+
+struct alignas(16) PackDev {
+    int32_t n_mem;            // members, 1..kMaxPack
+    int32_t nlanes;           // lanes used by all members
+    int32_t n_seg;            // replica sets of all members
+    int32_t ntest;            // exchange tests of all members (sum over sets of K (K - 1) / 2)
+    int32_t mem[kMaxPack];    // instance indices
+    int32_t lane0[kMaxPack];  // first lane of each member
+    int64_t cost;             // cells, used to order the work queue
+};
+
 // Metropolis and exchange tables of one temperature ladder.
 struct alignas(16) TableDev {
     int32_t K, lds_ts_entries;     // entries of the exchange fast table held in LDS

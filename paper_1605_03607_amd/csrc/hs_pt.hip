@@ -134,10 +134,33 @@ __device__ __forceinline__ void philox_rounds(uint32_t &x0, uint32_t &x1, uint32
     }
 }
 
+// (the key must be the same in every lane of the wavefront)
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1)
 {
     const RoundKeys K = round_keys(k0, k1);
+    philox_rounds(c0, c1, c2, c3, K, 0);
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// Round keys of a key that differs between lanes (packed launches: the
+// members' instances have their own first key word).
+__device__ __forceinline__ RoundKeys round_keys_lane(uint32_t k0, uint32_t k1)
+{
+    RoundKeys K;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        K.a[r] = k0 + uint32_t(r) * W0;
+        K.b[r] = in_vgpr(k1 + uint32_t(r) * W1);
+    }
+    return K;
+}
+
+// Philox4x32-10 with a key that may differ between lanes.
+__device__ __forceinline__ uint4 philox_lane(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                             uint32_t k1)
+{
+    const RoundKeys K = round_keys_lane(k0, k1);
     philox_rounds(c0, c1, c2, c3, K, 0);
     return make_uint4(c0, c1, c2, c3);
 }
@@ -199,10 +222,19 @@ __device__ __forceinline__ int wave_min(int v)
 // Dynamic LDS layout of the sweep kernel.
 struct LdsLayout {
     uint32_t S, ths, tshi, Eacc, perm, sacc, ux, xrow, stopv, misc, total;
+    // packed launches only: replica-set segments, exchange-test decodes,
+    // the members' coupling words and flip masks, threshold-row offsets
+    uint32_t seg, dec, jwl, lml, thia;
 };
 
-// mode 1: 2-byte threshold columns (else 4-byte: no two lanes share a bank).
-__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int r_max, int mode)
+// mode bit 0: 2-byte threshold columns (else 4-byte: no two lanes share a
+// bank).  mode bit 1: packed launch (instances sharing the lanes; r_max then
+// counts the replica sets of all members, ntest_max their exchange tests, and
+// the exchange tables stay in global memory).
+constexpr int kLdsPacked = 2;
+
+__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int r_max, int mode,
+                                                int ntest_max = 0)
 {
     LdsLayout l;
     uint32_t o = 0;
@@ -221,11 +253,26 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int
     l.ux = o;
     o += 64 * 4;                                  // uniforms of the exchange pass, pair r (K-1) + k
     l.xrow = o;
-    o += 2 * 64 * 4;                              // exchange-table row start and length of pair (k, k+1)
+    // exchange-table row start and length of pair (k, k+1); packed launches
+    // also the exact table's row start and length, by the pair's lower slot
+    o += ((mode & kLdsPacked) ? 4 : 2) * 64 * 4;
     l.stopv = o;
     o += uint32_t(r_max) * 64 * 4;                // run ends of the exchange pass, [set][start]
     l.misc = o;
     o += 16 * 4;
+    l.seg = l.dec = l.jwl = l.lml = l.thia = o;
+    if (mode & kLdsPacked) {
+        l.seg = o;
+        o += 2 * 64 * 4;                          // first slot and K of every replica set
+        l.thia = o;
+        o += 64 * 4;                              // Metropolis threshold row of every slot
+        l.dec = o;
+        o += ((uint32_t(ntest_max) + 3) / 4) * 16;  // exchange test q -> set << 16 | k << 8 | j
+        l.jwl = o;
+        o += uint32_t(kMaxPack) * uint32_t(ncell_max) * 16 * 4;  // coupling words [member][cell][2][8]
+        l.lml = o;
+        o += uint32_t(kMaxPack) * uint32_t(ncell_max) * 2 * 4;   // flip masks [member][cell][2]
+    }
     l.total = o;
     return l;
 }
@@ -233,8 +280,9 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int
 struct SweepArgs {
     const InstDev *inst;
     const TableDev *tabs;
+    const PackDev *packs;     // packed launches: the packs the queue hands out
     const uint32_t *ws32;     // workspace viewed as uint32
-    const int32_t *order;     // instance processing order (descending cost)
+    const int32_t *order;     // processing order of instances (of packs when packed), descending cost
     uint32_t *queue;          // work-queue counter
     uint64_t *spins;
     uint8_t *perm;
@@ -245,10 +293,11 @@ struct SweepArgs {
     int64_t *t;
     int32_t *stopped;
     int32_t n_inst;
+    int32_t n_items;          // work items of the queue: instances, or packs when packed
     int32_t swap_interval;
     int64_t n_sweeps;
     uint32_t flags;
-    int32_t ncell_max, tshi_max, r_max;
+    int32_t ncell_max, tshi_max, r_max, ntest_max;
     int32_t lds_ts_ok;        // 1 if every ladder's fast exchange table fits in LDS
     int32_t lds_mode;         // lds_layout mode
     uint8_t *walk;            // optional: temperature index per configuration after each exchange pass
@@ -394,6 +443,81 @@ __device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm
     }
 }
 
+// Packed launches: the replica sets (segments) of the members have their own
+// K and ladder.  Segment s holds slots seg_base[s] .. seg_base[s] + K_s - 1;
+// pair (k, k+1) of a segment is indexed by its lower slot p = seg_base[s] + k,
+// and ptab[p], ptab[64 + p], ptab[128 + p], ptab[192 + p] give that pair's
+// fast-table row (as a uint16 index into the workspace), its 16-bit row
+// length, the exact table's row (uint32 index) and its length.  The tests
+// are decoded once per pack: dec[q] = s << 16 | k << 8 | j.
+__device__ void exchange_stops_packed(int ntest, int wave, int nwaves, const uint32_t *dec, const int32_t *seg_base,
+                                      const int32_t *Es, const uint32_t *ux, const int32_t *ptab, int32_t *stopv,
+                                      const uint32_t *ws32)
+{
+    const int lane = threadIdx.x & 63;
+    if (wave * 64 >= ntest) return;
+    const uint16_t *g16 = reinterpret_cast<const uint16_t *>(ws32);
+    for (int base = wave * 64; base < ntest; base += nwaves * 64) {
+        const uint32_t dc = dec[min(base + lane, ntest - 1)];
+        const int sg = int(dc >> 16), k = int((dc >> 8) & 0xFFu), j = int(dc & 0xFFu);
+        const int b = seg_base[sg];
+        const int pr = b + k;
+        const int ex = Es[b + j];
+        const int ey = Es[pr + 1];
+        const uint32_t u = ux[pr];
+        const int row = ptab[pr], dh = ptab[64 + pr];
+        const int d = ex - ey;
+        const uint32_t h = g16[row + min(max(d, 1), max(dh, 1)) - 1];  // clamped into the row
+        const uint32_t th = d <= dh ? h : 0u;
+        const uint32_t u16 = u >> 16;
+        bool rej = d > 0 && u16 > th;
+        const bool tie = d > 0 && u16 == th;
+        if (__any(tie)) {  // rare: exact table
+            if (tie) {
+                const int dmx = ptab[192 + pr];
+                const uint32_t tf = d <= dmx ? ws32[ptab[128 + pr] + d - 1] : 0u;
+                rej = !(u < tf);
+            }
+        }
+        if (rej && base + lane < ntest) atomicMin(&stopv[sg * 64 + j], k);
+    }
+}
+
+// Step 2 of a packed launch: exchange_apply over segments of their own K;
+// sacc counts accepted exchanges by the pair's lower slot.
+__device__ void exchange_apply_packed(int n_seg, const int32_t *seg_base, const int32_t *seg_k, int wave, int nwaves,
+                                      int32_t *perm, uint32_t *sacc, int32_t *stopv)
+{
+    const int j = threadIdx.x & 63;
+    for (int sg = wave; sg < n_seg; sg += nwaves) {
+        const int base = __builtin_amdgcn_readfirstlane(seg_base[sg]);
+        const int K = __builtin_amdgcn_readfirstlane(seg_k[sg]);
+        int st = K - 1;
+        if (j < K - 1) {
+            st = stopv[sg * 64 + j];
+            stopv[sg * 64 + j] = K - 1;  // ready for the next pass
+        }
+        const int st2 = __shfl(st, min(st + 1, K - 1), 64);
+        uint64_t ends = 0;
+        int x0 = 0;
+        do {
+            const int e1 = __builtin_amdgcn_readlane(st, x0);
+            const int e2 = __builtin_amdgcn_readlane(st2, x0);
+            ends |= (1ull << e1) | (1ull << e2);
+            x0 = max(e2, x0) + 1;
+        } while (x0 < K);
+        if (j < K) {
+            const int e = j + __ffsll(static_cast<long long>(ends >> j)) - 1;
+            const uint64_t below = ends & ((1ull << j) - 1ull);
+            const int x = below ? 64 - __clzll(static_cast<long long>(below)) : 0;
+            const int ox = perm[base + x];
+            const int on = perm[base + min(j + 1, K - 1)];
+            perm[base + j] = j == e ? ox : on;
+            if (j < K - 1 && j != e) atomicAdd(&sacc[base + j], 1u);
+        }
+    }
+}
+
 __device__ __forceinline__ int wave_max(int v)
 {
 #pragma unroll
@@ -492,6 +616,33 @@ __device__ __forceinline__ int site_m4(uint32_t own, uint32_t oth, uint32_t xv, 
     return mul_spin<K>(own, dot4_acc(oth, jin, dot4_0(xv, jv)));
 }
 
+// The eight coupling words of cell side q (bytes -4 J towards the opposite
+// side, then towards the neighbouring cells) and its flip mask: scalar loads
+// from the workspace, or in a packed launch the copies of the lane's member
+// in LDS (lanes of different members read different words).
+template <bool kPacked>
+__device__ __forceinline__ uint32_t coupling_words(cptr<uint32_t> jw, cptr<uint32_t> livew, const uint32_t *jwl,
+                                                   const uint32_t *lml, uint32_t q, uint32_t (&jq)[8])
+{
+    if constexpr (kPacked) {
+        const uint4 lo = *reinterpret_cast<const uint4 *>(jwl + q * 8);
+        const uint4 hi = *reinterpret_cast<const uint4 *>(jwl + q * 8 + 4);
+        jq[0] = lo.x;
+        jq[1] = lo.y;
+        jq[2] = lo.z;
+        jq[3] = lo.w;
+        jq[4] = hi.x;
+        jq[5] = hi.y;
+        jq[6] = hi.z;
+        jq[7] = hi.w;
+        return lml[q];
+    } else {
+#pragma unroll
+        for (int w = 0; w < 8; ++w) jq[w] = jw[q * 8 + w];
+        return livew[q];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // The persistent sweep kernel.
 //
@@ -504,11 +655,11 @@ __device__ __forceinline__ int site_m4(uint32_t own, uint32_t oth, uint32_t xv, 
 // an exchange pass is due, the two exchange steps add two barriers.
 // kRecord: also write the temperature walk (pt_sweep_record); a separate
 // instantiation keeps the plain sweep free of the recording code.
-template <bool kRecord>
+template <bool kRecord, bool kPacked>
 __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
 {
     extern __shared__ __align__(16) char lds[];
-    const LdsLayout L = lds_layout(a.ncell_max, a.tshi_max, a.r_max, a.lds_mode);
+    const LdsLayout L = lds_layout(a.ncell_max, a.tshi_max, a.r_max, a.lds_mode, a.ntest_max);
     const uint32_t ths_sh = (a.lds_mode & 1) ? 5u : 6u;  // entry m of a column at byte (4 m) << ths_sh
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -532,25 +683,105 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         __syncthreads();
         const int qi = __builtin_amdgcn_readfirstlane(misc[0]);
         __syncthreads();
-        if (qi >= a.n_inst) break;
-        const int n = __builtin_amdgcn_readfirstlane(to_const(a.order)[qi]);
+        if (qi >= a.n_items) break;
+        const int item = __builtin_amdgcn_readfirstlane(to_const(a.order)[qi]);
+        // The first member (the only one unless packed) gives the lattice and
+        // the task tables; K, R, the Philox key and the tables of a lane come
+        // from the lane's own member.
+        PackDev pk{};
+        if constexpr (kPacked) {
+            pk = load_desc(a.packs + item);
+        } else {
+            pk.n_mem = 1;
+            pk.mem[0] = item;
+        }
+        const int n = pk.mem[0];
         const InstDev d = load_desc(a.inst + n);
         const TableDev tb = load_desc(a.tabs + d.tab);
-        const int K = d.K, R = d.R, nlanes = d.nlanes, ncell = d.ncell;
-        const uint32_t key0 = d.key0, key1 = d.key1;
+        const int ncell = d.ncell;
+        const uint32_t key1 = d.key1;
         const cptr<uint32_t> ws4 = to_const(a.ws32);
         const cptr<uint32_t> jw = ws4 + d.jw_off;     // coupling words [ncell][2][8]
         const cptr<uint32_t> livew = ws4 + d.live_off; // flip masks [ncell][2]
-        const uint64_t *sp = a.spins + d.spin_off;
+        // the lane's member: the second one from lane0[1] on (packed launches)
+        const InstDev e = kPacked && pk.n_mem > 1 ? load_desc(a.inst + pk.mem[1]) : d;
+        const TableDev te = kPacked && pk.n_mem > 1 ? load_desc(a.tabs + e.tab) : tb;
+        const int mi = (kPacked && pk.n_mem > 1 && lane >= pk.lane0[1]) ? 1 : 0;
+        const int K = mi ? e.K : d.K, R = mi ? e.R : d.R;
+        const int nlanes = kPacked ? pk.nlanes : d.nlanes;
+        const uint32_t key0 = mi ? e.key0 : d.key0;
+        const int lane0 = mi ? pk.lane0[1] : 0;  // first lane of this lane's member
+        const int nm = mi ? pk.mem[1] : n;       // this lane's instance
+        const int64_t spin_off = mi ? e.spin_off : d.spin_off;
+        const int64_t live_off = mi ? e.live_off : d.live_off;
+        const int64_t tfull_off = mi ? te.tfull_off : tb.tfull_off;
+        // packed: this lane's member's coupling words and flip masks in LDS
+        const uint32_t *jwl = reinterpret_cast<const uint32_t *>(lds + L.jwl) + mi * a.ncell_max * 16;
+        const uint32_t *lml = reinterpret_cast<const uint32_t *>(lds + L.lml) + mi * a.ncell_max * 2;
+        int32_t *seg_base = reinterpret_cast<int32_t *>(lds + L.seg);
+        int32_t *seg_k = seg_base + 64;
+        uint32_t *dec = reinterpret_cast<uint32_t *>(lds + L.dec);
+        if constexpr (kPacked) {
+            // the members' coupling words and flip masks
+            for (int m = 0; m < pk.n_mem; ++m) {
+                const InstDev &x = m ? e : d;
+                uint32_t *jd = reinterpret_cast<uint32_t *>(lds + L.jwl) + m * a.ncell_max * 16;
+                uint32_t *ld = reinterpret_cast<uint32_t *>(lds + L.lml) + m * a.ncell_max * 2;
+                for (int i = tid; i < ncell * 16; i += blockDim.x) jd[i] = a.ws32[x.jw_off + i];
+                for (int i = tid; i < ncell * 2; i += blockDim.x) ld[i] = a.ws32[x.live_off + i];
+            }
+            if (tid < 64) {
+                // per slot l: threshold row, exchange-table rows of pair (k, k+1), perm, counters
+                const int l = tid;
+                const bool lv = l < pk.nlanes;
+                const int ll = l - lane0;
+                const int kk = lv ? ll % K : 0, rr = lv ? ll / K : 0;
+                const TableDev &tl = mi ? te : tb;
+                uint32_t *thia = reinterpret_cast<uint32_t *>(lds + L.thia);
+                thia[l] = uint32_t(tl.thi_off + kk * kMRow);
+                const bool pair = lv && kk < K - 1;
+                xrow[l] = pair ? int32_t(tl.ts_hi_off * 2 + a.ws32[tl.ts_row_off + kk]) : 0;
+                xrow[64 + l] = pair ? int32_t(a.ws32[tl.ts_dhi_off + kk]) : 0;
+                xrow[128 + l] = pair ? int32_t(tl.ts_full_off + a.ws32[tl.ts_full_row_off + kk]) : 0;
+                xrow[192 + l] = pair ? int32_t(a.ws32[tl.ts_dmax_off + kk]) : 0;
+                // perm in LDS is set-major (slot lane0 + r K + k, configuration columns of
+                // the member from lane0 on); the buffers hold slot k R + r
+                perm[l] = lv ? lane0 + int(a.perm[nm * 64 + kk * R + rr]) : l;
+                sacc[l] = pair ? a.swap_acc[nm * 64 + kk * R + rr] : 0u;
+                if (lv && kk == 0) {  // first slot of a replica set: its segment
+                    const int sg = (mi ? d.R : 0) + rr;
+                    seg_base[sg] = l;
+                    seg_k[sg] = K;
+                }
+            }
+            if (tid == 0) misc[1] = 0;
+            __syncthreads();
+            // exchange tests of every set, and the run ends, from the segments
+            for (int q = tid; q < pk.ntest; q += blockDim.x) {
+                int sg = 0, rem = q;
+                while (rem >= seg_k[sg] * (seg_k[sg] - 1) / 2) {
+                    rem -= seg_k[sg] * (seg_k[sg] - 1) / 2;
+                    ++sg;
+                }
+                int k = int((__fsqrt_rn(float(8 * rem + 1)) - 1.0f) * 0.5f);
+                k += ((k + 1) * (k + 2) / 2 <= rem) ? 1 : 0;
+                k -= (k * (k + 1) / 2 > rem) ? 1 : 0;
+                dec[q] = (uint32_t(sg) << 16) | (uint32_t(k) << 8) | uint32_t(rem - k * (k + 1) / 2);
+            }
+            for (int i = tid; i < pk.n_seg * 64; i += blockDim.x) stopv[i] = seg_k[i >> 6] - 1;
+        }
+        const uint64_t *sp = a.spins + spin_off;
 
         // ---- load state ----
         for (int q = wave; q < ncell * 2; q += nwaves) {
-            const uint32_t lm = livew[q];
+            const uint32_t lm = kPacked ? a.ws32[live_off + q] : livew[q];
             uint32_t w = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint64_t word = sp[q * 4 + k];
-                const uint32_t bit = ((lm >> (8 * k + 1)) & 1u) ? uint32_t((word >> lane) & 1ull) : 0u;
+                const bool in = !kPacked || lane < nlanes;
+                const uint32_t bit =
+                    (in && ((lm >> (8 * k + 1)) & 1u)) ? uint32_t((word >> (lane - lane0)) & 1ull) : 0u;
                 w |= (bit ? 0xFFu : 0x01u) << (8 * k);
             }
             S[q * 64 + lane] = w;
@@ -561,26 +792,33 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         // gathers from distinct banks
         for (int i = tid; i < kMRow * 64; i += blockDim.x) {
             const int m = i >> 6, sx = i & 63;
-            const int k = sx < nlanes ? sx % K : 0;
-            const uint32_t th = a.ws32[tb.thi_off + k * kMRow + m];
+            uint32_t th;
+            if constexpr (kPacked) {
+                th = a.ws32[reinterpret_cast<const uint32_t *>(lds + L.thia)[sx] + m];
+            } else {
+                const int k = sx < nlanes ? sx % K : 0;
+                th = a.ws32[tb.thi_off + k * kMRow + m];
+            }
             // 0x10000 ("always", m <= 0) becomes 0xFFFF: a uniform of 0xFFFF then
             // ties and the exact pass accepts
             THS[(uint32_t(i) << ths_sh) >> 5] = uint16_t((th >= 0x10000u ? 0xFFFFu : th) ^ 0x8000u);
         }
-        if (a.lds_ts_ok) {
-            const uint32_t *src = a.ws32 + tb.ts_hi_off;
-            uint32_t *dst = reinterpret_cast<uint32_t *>(tshi);
-            for (int i = tid; i < (tb.lds_ts_entries + 1) / 2; i += blockDim.x) dst[i] = src[i];
+        if constexpr (!kPacked) {
+            if (a.lds_ts_ok) {
+                const uint32_t *src = a.ws32 + tb.ts_hi_off;
+                uint32_t *dst = reinterpret_cast<uint32_t *>(tshi);
+                for (int i = tid; i < (tb.lds_ts_entries + 1) / 2; i += blockDim.x) dst[i] = src[i];
+            }
+            for (int i = tid; i < R * 64; i += blockDim.x) stopv[i] = K - 1;
+            load_xrows(xrow, tb, a.ws32, K, tid);
+            if (tid < 64) {
+                // perm in LDS is set-major (slot r K + k); the buffer holds slot k R + r
+                const int src = tid < K * R ? (tid % K) * R + tid / K : tid;
+                perm[tid] = a.perm[n * 64 + src];
+                sacc[tid] = a.swap_acc[n * 64 + tid];
+            }
+            if (tid == 0) misc[1] = a.stopped[n];
         }
-        for (int i = tid; i < R * 64; i += blockDim.x) stopv[i] = K - 1;
-        load_xrows(xrow, tb, a.ws32, K, tid);
-        if (tid < 64) {
-            // perm in LDS is set-major (slot r K + k); the buffer holds slot k R + r
-            const int src = tid < K * R ? (tid % K) * R + tid / K : tid;
-            perm[tid] = a.perm[n * 64 + src];
-            sacc[tid] = a.swap_acc[n * 64 + tid];
-        }
-        if (tid == 0) misc[1] = a.stopped[n];
         __syncthreads();
 
         // Lane l is slot l = r K + k (temperature k of replica set r) in every
@@ -588,8 +826,8 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         // which changes only in exchange passes.  Dead lanes keep their own
         // (unused) column.
         const bool live = lane < nlanes;
-        const int kslot = live ? lane % K : 0;
-        const uint32_t sword = live ? (uint32_t(kslot) << 8) | uint32_t(lane / K) : 0u;
+        const int kslot = live ? (lane - lane0) % K : 0;
+        const uint32_t sword = live ? (uint32_t(kslot) << 8) | uint32_t((lane - lane0) / K) : 0u;
         // threshold column of this lane's temperature
         // (with 4-byte columns every lane of a gather reads its own bank)
         const uint32_t thl_base = L.ths + ((uint32_t(kMaxM) * 4u) << ths_sh) + ((uint32_t(lane) << ths_sh) >> 4);
@@ -601,12 +839,12 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             ml.lo = l;
         }
         int col = live ? perm[lane] : lane;
-        int Es = live ? a.energy[n * 64 + col] : 0;  // energy of slot `lane` after the last sweep
-        int col_e = col;                              // the column Es belongs to
-        const int set = live ? lane / K : 0;
-        const int seg_lo = set * K, seg_hi = seg_lo + K;
-        int em = a.emin[n * 64 + set];
-        int64_t th = a.thit[n * 64 + set];
+        int Es = live ? a.energy[nm * 64 + col - lane0] : 0;  // energy of slot `lane` after the last sweep
+        int col_e = col;                                       // the column Es belongs to
+        const int set = live ? (lane - lane0) / K : 0;          // the lane's replica set in its instance
+        const int seg_lo = lane0 + set * K, seg_hi = seg_lo + K;
+        int em = a.emin[nm * 64 + set];
+        int64_t th = a.thit[nm * 64 + set];
         int agree = 0;
         int64_t tmax = 0;
         if (stop_mode) {
@@ -626,12 +864,13 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         // Metropolis draws: the last round's keys carry the bias kBias16 of
         // the 16-bit comparisons, so words 0 and 2 come out biased (the exact
         // pass removes it again)
-        RoundKeys RK = round_keys(key0, key1);
+        RoundKeys RK = kPacked ? round_keys_lane(key0, key1) : round_keys(key0, key1);
         RK.a[9] ^= kBias16;
         RK.b[9] ^= kBias16;
         const int tri = d.tri;
         const uint32_t tri_m = d.tri_m;
-        const uint32_t xdec = exchange_test(min(tid, max(tri * R - 1, 0)), tri, tri_m);  // this lane's first test
+        // this lane's first test (unpacked; packed launches decode through dec[])
+        const uint32_t xdec = kPacked ? 0u : exchange_test(min(tid, max(tri * R - 1, 0)), tri, tri_m);
 
         // Philox draws do not depend on the exchange passes, since a lane's
         // slot is fixed.  The draws of the first two pairs of phase 0 are made
@@ -639,11 +878,11 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         // wavefronts that do not walk the runs.  Every other draw (the next
         // pair of the phase, or the first pair of phase 1) is computed while
         // the spin rows of the current pair are being read.
-        const int nwalk = min(R, nwaves);  // wavefronts of the exchange walk
+        const int nwalk = min(kPacked ? pk.n_seg : R, nwaves);  // wavefronts of the exchange walk
         uint4 pre0 = make_uint4(0u, 0u, 0u, 0u), pre1 = pre0;
         auto predraw = [&](const MetroUniform &m) {
-            if (nt > 0) pre0 = metro_call(ml, m, task[(wave * 2) * iters * 8], RK);
-            if (nt > 1) pre1 = metro_call(ml, m, task[((wave * 2) * iters + 1) * 8], RK);
+            if (nt > 0) pre0 = metro_call(ml, m, task[(wave * 2) * iters * 16], RK);
+            if (nt > 1) pre1 = metro_call(ml, m, task[((wave * 2) * iters + 1) * 16], RK);
         };
         predraw(metro_uniform(uint32_t(t), kUseMetroHi, key0, key1));
         int64_t n_ex = 0;  // exchange passes made in this launch (recording only)
@@ -667,19 +906,18 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                 __builtin_amdgcn_s_setprio(3);
                 for (int it = 0; it < nt; ++it) {
                     // task entry: counter word, quad indices, spin rows (scalar loads)
-                    const cptr<uint32_t> te = task + ((wave * 2 + p) * iters + it) * 8;
+                    const cptr<uint32_t> te = task + ((wave * 2 + p) * iters + it) * 16;
                     const uint32_t c1 = te[0];
                     const uint32_t qq = te[1];
                     const bool second = (qq >> 16) != 0xFFFFu;
                     uint32_t orow[2], o0[2], oth[2], A[2], B[2];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const uint32_t roo = te[2 + 2 * h], rab = te[3 + 2 * h];
-                        orow[h] = s_base + ((roo & 0xFFFFu) << 8);
+                        orow[h] = s_base + te[2 + 4 * h];
                         o0[h] = *reinterpret_cast<const uint32_t *>(lds + orow[h]);
-                        oth[h] = *reinterpret_cast<const uint32_t *>(lds + s_base + ((roo >> 16) << 8));
-                        A[h] = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab & 0xFFFFu) << 8));
-                        B[h] = *reinterpret_cast<const uint32_t *>(lds + s_base + ((rab >> 16) << 8));
+                        oth[h] = *reinterpret_cast<const uint32_t *>(lds + s_base + te[3 + 4 * h]);
+                        A[h] = *reinterpret_cast<const uint32_t *>(lds + s_base + te[4 + 4 * h]);
+                        B[h] = *reinterpret_cast<const uint32_t *>(lds + s_base + te[5 + 4 * h]);
                     }
                     const uint4 rw = rw_next;
                     {
@@ -687,7 +925,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         if (p == 0 && it == 0 && !last) {
                             rw_next = pre1;
                         } else if (p == 0 || !last) {
-                            const uint32_t c1n = !last ? te[8] : task[((wave * 2 + 1) * iters) * 8];
+                            const uint32_t c1n = !last ? te[16] : task[((wave * 2 + 1) * iters) * 16];
                             rw_next = metro_call(ml, mu, c1n, RK);
                         }
                     }
@@ -698,8 +936,8 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const uint32_t q = (h == 0 || !second) ? (qq & 0xFFFFu) : (qq >> 16);
-                        const cptr<uint32_t> jq = jw + q * 8;
-                        const uint32_t fm = livew[q];
+                        uint32_t jq[8];
+                        const uint32_t fm = coupling_words<kPacked>(jw, livew, jwl, lml, q, jq);
                         const uint32_t x01 = __builtin_amdgcn_perm(B[h], A[h], 0x05040100u);
                         const uint32_t x23 = __builtin_amdgcn_perm(B[h], A[h], 0x07060302u);
                         const int m0 = site_m4<0>(o0[h], oth[h], x01, jq[0], jq[4]);
@@ -734,12 +972,13 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         const uint4 rlb = metro_call(ml, mlo, c1, RK);
                         const uint4 rl = make_uint4(rlb.x ^ kBias16, rlb.y, rlb.z ^ kBias16, rlb.w);
                         const uint4 rh = make_uint4(rw.x ^ kBias16, rw.y, rw.z ^ kBias16, rw.w);
-                        const uint32_t *tfull = a.ws32 + tb.tfull_off + kslot * kMRow + kMaxM;
+                        const uint32_t *tfull = a.ws32 + tfull_off + kslot * kMRow + kMaxM;
                         e4 = e4_save;
                         nrej = nrej_save;
                         for (int h = 0; h < 2; ++h) {
                             const uint32_t q = (h == 0 || !second) ? (qq & 0xFFFFu) : (qq >> 16);
-                            const cptr<uint32_t> jq = jw + q * 8;
+                            uint32_t jq[8];
+                            const uint32_t fmq = coupling_words<kPacked>(jw, livew, jwl, lml, q, jq);
                             const uint32_t x01 = __builtin_amdgcn_perm(B[h], A[h], 0x05040100u);
                             const uint32_t x23 = __builtin_amdgcn_perm(B[h], A[h], 0x07060302u);
                             int m[4];
@@ -756,7 +995,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                                 ev += acc ? m[k] : -m[k];
                             }
                             if (p == 1 && (h == 0 || second)) e4 += ev;
-                            nw[h] = o0[h] ^ (flip & livew[q]);  // flip bytes 0xFE, fm bytes 0xFE
+                            nw[h] = o0[h] ^ (flip & fmq);  // flip bytes 0xFE, fm bytes 0xFE
                         }
                     }
                     *reinterpret_cast<uint32_t *>(lds + orow[0]) = nw[0];
@@ -770,7 +1009,14 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                 }
                 if (p == 1 && live) atomicAdd(&Eb[lane], (e4 + int(nrej >> 3)) >> 2);
                 // the uniforms of a due exchange pass, drawn by the last wavefront
-                if (p == 1 && cd == 0 && wave == nwaves - 1) ux[lane] = exchange_uniform(tt, kUseSwap, K, R, key0, key1);
+                if (p == 1 && cd == 0 && wave == nwaves - 1) {
+                    if constexpr (kPacked)  // by slot: pair (k, k+1) of a set at its lower slot
+                        ux[lane] = (live && kslot < K - 1)
+                                       ? philox_lane(tt, uint32_t(kslot), uint32_t(set), kUseSwap, key0, key1).x
+                                       : 0u;
+                    else
+                        ux[lane] = exchange_uniform(tt, kUseSwap, K, R, key0, key1);
+                }
                 __syncthreads();
             }
             // ---- energies, running minima, agreement, exchange ----
@@ -796,7 +1042,9 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             }
             const bool stop_now = stop_mode && agree && (t + 1) >= 2 * tmax;
             if (cd == 0) {
-                if (a.lds_ts_ok)
+                if constexpr (kPacked)
+                    exchange_stops_packed(pk.ntest, wave, nwaves, dec, seg_base, Eb, ux, xrow, stopv, a.ws32);
+                else if (a.lds_ts_ok)
                     exchange_stops<true>(K, R, tri, tri_m, wave, nwaves, xdec, Eb, ux, xrow, stopv, tb, a.ws32,
                                          tshi);
                 else
@@ -804,14 +1052,17 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                                           tshi);
                 __syncthreads();
                 if (wave >= nwalk) predraw(mu_next);
-                exchange_apply(K, R, wave, nwaves, perm, sacc, stopv);
+                if constexpr (kPacked)
+                    exchange_apply_packed(pk.n_seg, seg_base, seg_k, wave, nwaves, perm, sacc, stopv);
+                else
+                    exchange_apply(K, R, wave, nwaves, perm, sacc, stopv);
                 __syncthreads();
                 if (wave < nwalk) predraw(mu_next);
                 col = live ? perm[lane] : lane;
                 if constexpr (kRecord) {
                     // temperature walk: configuration col now sits at temperature kslot
                     if (wave == nwaves - 1 && n_ex < a.walk_cap && live)
-                        a.walk[(int64_t(n) * a.walk_cap + n_ex) * 64 + col] = uint8_t(kslot);
+                        a.walk[(int64_t(nm) * a.walk_cap + n_ex) * 64 + col - lane0] = uint8_t(kslot);
                     ++n_ex;
                 }
             } else {
@@ -823,6 +1074,43 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         }
 
         // ---- store state ----
+        if constexpr (kPacked) {
+            for (int m = 0; m < pk.n_mem; ++m) {
+                // member m's lanes lane0[m] .. lane0[m] + K R - 1, its own words
+                const InstDev x = load_desc(a.inst + pk.mem[m]);
+                const int l0 = pk.lane0[m];
+                uint64_t *spm = a.spins + x.spin_off;
+                const cptr<uint32_t> lvm = ws4 + x.live_off;
+                const uint64_t mmask = x.nlanes >= 64 ? ~0ull : ((1ull << x.nlanes) - 1ull);
+                for (int q = wave; q < ncell * 2; q += nwaves) {
+                    const uint32_t w = S[q * 64 + lane];
+                    const uint32_t lm = lvm[q];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint64_t bits = (__ballot(((w >> (8 * k)) & 0xFFu) == 0xFFu) >> l0) & mmask;
+                        if (lane == k) spm[q * 4 + k] = ((lm >> (8 * k + 1)) & 1u) ? bits : 0ull;
+                    }
+                }
+            }
+            if (wave == 0) {
+                if (live) {
+                    const int rr = (lane - lane0) / K;
+                    a.energy[nm * 64 + col_e - lane0] = Es;
+                    a.perm[nm * 64 + kslot * R + rr] = uint8_t(perm[lane] - lane0);
+                    if (kslot < K - 1) a.swap_acc[nm * 64 + kslot * R + rr] = sacc[lane];
+                    if (kslot == 0) {
+                        a.emin[nm * 64 + rr] = em;
+                        a.thit[nm * 64 + rr] = th;
+                    }
+                }
+                if (lane < pk.n_mem) {
+                    a.t[pk.mem[lane]] = t;
+                    a.stopped[pk.mem[lane]] = 0;
+                }
+            }
+            __syncthreads();
+            continue;
+        }
         uint64_t *spw = a.spins + d.spin_off;
         const uint64_t lane_mask = nlanes >= 64 ? ~0ull : ((1ull << nlanes) - 1ull);
         for (int q = wave; q < ncell * 2; q += nwaves) {
@@ -1015,12 +1303,15 @@ struct hs_pt {
     int32_t swap_interval = 0;
     int nwaves = 16;
     int grid = 0;
-    int ncell_max = 0, tshi_max = 0, r_max = 1;
+    int ncell_max = 0, tshi_max = 0, r_max = 1, ntest_max = 0;
     int lds_ts_ok = 1;
     int lds_mode = 0;
+    bool packed = false;  // the queue hands out packs of instances sharing the lanes
+    int n_items = 0;      // work items of the queue
+    int64_t lane_sites = 0;  // sum over work items of 64 x sites: the lane slots of one sweep
     size_t lds_bytes = 0;
-    // workspace layout (byte offsets)
-    size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0;
+    // workspace layout (uint32 offsets)
+    size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0, off_packs = 0;
     std::vector<uint32_t> host_ws;  // staging image of the workspace (kept until destroy)
     hipEvent_t uploaded = nullptr;  // recorded after the upload of host_ws on `stream`
 };
@@ -1037,14 +1328,55 @@ struct Plan {
     std::vector<InstDev> idev;
     std::vector<TableDev> tdev;
     std::vector<int32_t> order;
+    std::vector<PackDev> packs;   // packed launches only
     std::vector<uint32_t> image;  // workspace image in uint32 words
     int nwaves = 16;
-    size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0;
-    int ncell_max = 0, K_max = 0, tshi_max = 0, r_max = 1;
+    size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0, off_packs = 0;
+    int ncell_max = 0, K_max = 0, tshi_max = 0, r_max = 1, ntest_max = 0;
     int lds_ts_ok = 1;
     int lds_mode = 0;
+    bool packed = false;
     size_t total_words = 0;
 };
+
+// Packs of instances sharing a workgroup's lanes: within each lattice size,
+// the instance with the most lanes is paired with the one with the fewest
+// if their lanes fit into 64 together, else it runs alone (a two-pointer
+// pass over the lane counts, which pairs as many as pairing can).
+void make_packs(const std::vector<InstDev> &idev, std::vector<PackDev> &packs)
+{
+    packs.clear();
+    for (int L = 1; L <= HS_MAX_L; ++L) {
+        std::vector<int> ids;
+        for (int i = 0; i < int(idev.size()); ++i)
+            if (idev[i].L == L) ids.push_back(i);
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return idev[a].nlanes < idev[b].nlanes; });
+        int lo = 0, hi = int(ids.size()) - 1;
+        while (lo <= hi) {
+            PackDev pk;
+            std::memset(&pk, 0, sizeof(pk));
+            const InstDev &big = idev[ids[hi]];
+            pk.mem[0] = ids[hi];
+            pk.n_mem = 1;
+            pk.nlanes = big.nlanes;
+            pk.n_seg = big.R;
+            pk.ntest = big.R * big.K * (big.K - 1) / 2;
+            if (lo < hi && big.nlanes + idev[ids[lo]].nlanes <= HS_MAX_LANES) {
+                const InstDev &sm = idev[ids[lo]];
+                pk.mem[1] = ids[lo];
+                pk.lane0[1] = big.nlanes;
+                pk.n_mem = 2;
+                pk.nlanes += sm.nlanes;
+                pk.n_seg += sm.R;
+                pk.ntest += sm.R * sm.K * (sm.K - 1) / 2;
+                ++lo;
+            }
+            pk.cost = int64_t(big.ncell);
+            packs.push_back(pk);
+            --hi;
+        }
+    }
+}
 
 size_t align16w(size_t w) { return (w + 3) & ~size_t(3); }
 
@@ -1094,6 +1426,10 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
     }
     if (d.block_waves < 0 || d.block_waves > 16) {
         err = "block_waves must be in 0..16";
+        return HS_EINVAL;
+    }
+    if ((d.flags & HS_PACK_LANES) && (d.flags & HS_STOP_ON_AGREEMENT)) {
+        err = "HS_PACK_LANES cannot be combined with HS_STOP_ON_AGREEMENT";
         return HS_EINVAL;
     }
     const int n = d.n_inst;
@@ -1214,9 +1550,33 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
         x.ts_full_row_off = int64_t(append(img, h.ts_full_row.data(), h.ts_full_row.size()));
         P.tshi_max = std::max(P.tshi_max, int(h.ts_hi.size()));
     }
+    // Packed launch: the packs, their LDS layout (exchange tables stay in
+    // global memory); kept only if it fits, packs something, and every
+    // workspace offset fits the 32-bit indices of the packed exchange tables
+    if (d.flags & HS_PACK_LANES) {
+        make_packs(P.idev, P.packs);
+        int nseg = 1, ntest = 0;
+        for (const PackDev &pk : P.packs) {
+            nseg = std::max(nseg, pk.n_seg);
+            ntest = std::max(ntest, pk.ntest);
+        }
+        const int modes[2] = {0, 1};
+        for (int m : modes)
+            if (!P.packed && P.packs.size() < size_t(n) &&
+                dev::lds_layout(P.ncell_max, 0, nseg, m | dev::kLdsPacked, ntest).total <= kLdsLimit &&
+                img.size() < (size_t(1) << 29)) {
+                P.packed = true;
+                P.lds_mode = m | dev::kLdsPacked;
+                P.lds_ts_ok = 0;
+                P.tshi_max = 0;
+                P.r_max = nseg;
+                P.ntest_max = ntest;
+            }
+        if (!P.packed) P.packs.clear();
+    }
     // LDS layout: the fast exchange table in LDS first, then 4-byte threshold
     // columns, whichever fit
-    {
+    if (!P.packed) {
         const int modes[2] = {0, 1};
         bool found = false;
         if (size_t(P.tshi_max) * 2 <= kLdsTsBudget) {
@@ -1240,14 +1600,20 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
             return HS_EUNSUPPORTED;
         }
     }
-    // order: most expensive first
-    P.order.resize(n);
+    // order: most expensive first (instances, or packs)
+    const int items = P.packed ? int(P.packs.size()) : n;
+    P.order.resize(items);
     std::iota(P.order.begin(), P.order.end(), 0);
-    std::stable_sort(P.order.begin(), P.order.end(),
-                     [&](int a, int b) { return P.idev[a].cost > P.idev[b].cost; });
+    if (P.packed)
+        std::stable_sort(P.order.begin(), P.order.end(),
+                         [&](int a, int b) { return P.packs[a].cost > P.packs[b].cost; });
+    else
+        std::stable_sort(P.order.begin(), P.order.end(),
+                         [&](int a, int b) { return P.idev[a].cost > P.idev[b].cost; });
+    if (P.packed) P.off_packs = append(img, P.packs.data(), P.packs.size());
     std::memcpy(img.data() + P.off_inst, P.idev.data(), sizeof(InstDev) * n);
     std::memcpy(img.data() + P.off_tabs, P.tdev.data(), sizeof(TableDev) * P.tdev.size());
-    std::memcpy(img.data() + P.off_order, P.order.data(), sizeof(int32_t) * n);
+    std::memcpy(img.data() + P.off_order, P.order.data(), sizeof(int32_t) * items);
     P.total_words = align16w(img.size());
     img.resize(P.total_words, 0u);
     return HS_OK;
@@ -1326,11 +1692,19 @@ int hs::pt_init_ex(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *
     h->r_max = P.r_max;
     h->lds_ts_ok = P.lds_ts_ok;
     h->lds_mode = P.lds_mode;
+    h->packed = P.packed;
+    h->ntest_max = P.ntest_max;
+    h->n_items = P.packed ? int(P.packs.size()) : d->n_inst;
+    if (P.packed)
+        for (const PackDev &pk : P.packs) h->lane_sites += 64 * int64_t(P.idev[pk.mem[0]].n_sites);
+    else
+        for (const InstDev &x : P.idev) h->lane_sites += 64 * int64_t(x.n_sites);
     h->off_inst = P.off_inst;
     h->off_tabs = P.off_tabs;
     h->off_order = P.off_order;
     h->off_queue = P.off_queue;
-    h->lds_bytes = dev::lds_layout(h->ncell_max, h->tshi_max, h->r_max, h->lds_mode).total;
+    h->off_packs = P.off_packs;
+    h->lds_bytes = dev::lds_layout(h->ncell_max, h->tshi_max, h->r_max, h->lds_mode, h->ntest_max).total;
     h->host_ws = std::move(P.image);
     if (h->n_inst == 0) {
         *out = h;
@@ -1364,8 +1738,10 @@ int hs::pt_init_ex(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *
     hipLaunchKernelGGL(dev::k_pt_init, dim3(h->n_inst), dim3(64), 0, h->stream, ia);
     e = hipGetLastError();
     if (e != hipSuccess) return abort_init(hip_fail(e, "pt_init: launch"));
-    const void *kfn = reinterpret_cast<const void *>(&dev::k_pt_sweep<false>);
-    const void *kfn_rec = reinterpret_cast<const void *>(&dev::k_pt_sweep<true>);
+    const void *kfn = h->packed ? reinterpret_cast<const void *>(&dev::k_pt_sweep<false, true>)
+                                : reinterpret_cast<const void *>(&dev::k_pt_sweep<false, false>);
+    const void *kfn_rec = h->packed ? reinterpret_cast<const void *>(&dev::k_pt_sweep<true, true>)
+                                    : reinterpret_cast<const void *>(&dev::k_pt_sweep<true, false>);
     if (h->lds_bytes > 64 * 1024) {
         e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(h->lds_bytes));
         if (e == hipSuccess)
@@ -1376,7 +1752,7 @@ int hs::pt_init_ex(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, h->nwaves * 64, h->lds_bytes);
     if (e != hipSuccess || per_cu < 1)
         return abort_init(fail(HS_EUNSUPPORTED, "pt_init: instances too large for one workgroup's LDS"));
-    h->grid = std::min(h->n_inst, per_cu * device_cus());
+    h->grid = std::min(h->n_items, per_cu * device_cus());
     *out = h;
     return HS_OK;
 }
@@ -1391,6 +1767,7 @@ int sweep_launch(hs_pt *h, int64_t n_sweeps, hipStream_t stream, uint8_t *walk =
     dev::SweepArgs a;
     a.inst = reinterpret_cast<const InstDev *>(ws + h->off_inst * 4);
     a.tabs = reinterpret_cast<const TableDev *>(ws + h->off_tabs * 4);
+    a.packs = reinterpret_cast<const PackDev *>(ws + h->off_packs * 4);
     a.ws32 = reinterpret_cast<const uint32_t *>(ws);
     a.order = reinterpret_cast<const int32_t *>(ws + h->off_order * 4);
     a.queue = reinterpret_cast<uint32_t *>(ws + h->off_queue * 4);
@@ -1403,21 +1780,28 @@ int sweep_launch(hs_pt *h, int64_t n_sweeps, hipStream_t stream, uint8_t *walk =
     a.t = h->buf.t;
     a.stopped = h->buf.stopped;
     a.n_inst = h->n_inst;
+    a.n_items = h->n_items;
     a.swap_interval = h->swap_interval;
     a.n_sweeps = n_sweeps;
     a.flags = h->flags;
     a.ncell_max = h->ncell_max;
     a.tshi_max = h->tshi_max;
     a.r_max = h->r_max;
+    a.ntest_max = h->ntest_max;
     a.lds_ts_ok = h->lds_ts_ok;
     a.lds_mode = h->lds_mode;
     a.walk = walk;
     a.walk_cap = walk_cap;
     hipLaunchKernelGGL(dev::k_reset_queue, dim3(1), dim3(1), 0, stream, a.queue);
-    if (walk != nullptr)
-        hipLaunchKernelGGL(dev::k_pt_sweep<true>, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, stream, a);
+    const dim3 grid(h->grid), block(h->nwaves * 64);
+    if (walk != nullptr && h->packed)
+        hipLaunchKernelGGL((dev::k_pt_sweep<true, true>), grid, block, h->lds_bytes, stream, a);
+    else if (walk != nullptr)
+        hipLaunchKernelGGL((dev::k_pt_sweep<true, false>), grid, block, h->lds_bytes, stream, a);
+    else if (h->packed)
+        hipLaunchKernelGGL((dev::k_pt_sweep<false, true>), grid, block, h->lds_bytes, stream, a);
     else
-        hipLaunchKernelGGL(dev::k_pt_sweep<false>, dim3(h->grid), dim3(h->nwaves * 64), h->lds_bytes, stream, a);
+        hipLaunchKernelGGL((dev::k_pt_sweep<false, false>), grid, block, h->lds_bytes, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "pt_sweep: launch");
     return HS_OK;
@@ -1620,12 +2004,15 @@ int pt_destroy(hs_pt *h)
     return rc;
 }
 
-int pt_launch_shape(const hs_pt *h, int32_t *grid, int32_t *block_waves, int32_t *lds_bytes)
+int pt_launch_shape(const hs_pt *h, int32_t *grid, int32_t *block_waves, int32_t *lds_bytes, int32_t *work_items,
+                    int64_t *lane_sites)
 {
     if (h == nullptr) return fail(HS_EINVAL, "pt_launch_shape: NULL handle");
     if (grid) *grid = h->grid;
     if (block_waves) *block_waves = h->nwaves;
     if (lds_bytes) *lds_bytes = int32_t(h->lds_bytes);
+    if (work_items) *work_items = h->n_items;
+    if (lane_sites) *lane_sites = h->lane_sites;
     return HS_OK;
 }
 

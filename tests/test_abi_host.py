@@ -299,4 +299,4 @@ def test_closely_spaced_ladder_keeps_the_exchange_table_bounded():
 def test_destroy_of_a_null_handle_is_a_no_op():
     hs = _hs()
     assert hs.lib().pt_destroy(None) == 0
-    assert hs.lib().pt_launch_shape(None, None, None, None) == -1
+    assert hs.lib().pt_launch_shape(None, None, None, None, None, None) == -1
