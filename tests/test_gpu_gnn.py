@@ -147,3 +147,74 @@ def test_training_reduces_the_loss():
     for _ in range(150):
         last = sur.train_step(labels, lr=3e-3)[0]
     assert last < first / 5, (first, last)
+
+
+def test_trained_network_ranks_proposals_better_than_random():
+    """What the trained network gains over the search without it: ranking
+    the 16 one-coupler proposals of a parent (Algorithm 1's move, +-1..+-7)
+    by predicted ln TTS.  144 parents (seed instances after 0..39 random
+    mutations) and their 16 children are scored by PT with the search's
+    hardness_eval (common restart streams per parent, so a child's label is
+    comparable with its parent's); the network is trained by its own GPU
+    kernels on the (J, ln TTS) pairs of 96 parents and their children, and
+    on each of the 48 held-out parents the Spearman rank correlation between
+    predicted and PT-measured changes of ln TTS is taken.  Random ranking
+    has expected correlation 0; the network's mean over held-out parents
+    must exceed it by 0.03.  Measured: 0.075 to 0.10 (training sums
+    gradients with float atomics, so runs differ slightly; standard error
+    over parents 0.034), against 0.14 for the |J_new| - |J_old| heuristic:
+    the network gains a little over random screening and less than that
+    one-line rule.  The correlations of the network, of a fixed-seed random
+    ranking and of the heuristic are printed."""
+    from scipy import stats
+    hs = _gpu()
+    import paper_1605_03607_amd as P
+    from paper_1605_03607_amd import search as S
+    cfg = S.SearchConfig(mode="surrogate")
+    A = S.ALPHABET_PM7
+    rng = np.random.default_rng(11)
+    n_par, n_child, n_train = 144, 16, 96
+    parents = []
+    for i, J in enumerate(workloads.search_seeds(n_par, seed=777)):
+        J = J.copy()
+        for s in range(int(rng.integers(0, 40))):
+            e, _, new, _ = hs.instance_mutate(dict(L=8, J=J, live=None), A, 5000 + i, cfg.seed, s, 0)
+            J[e] = new
+        parents.append(J)
+    cands, meta = [], []
+    for i, J in enumerate(parents):
+        cands.append(dict(L=8, J=J, live=None, instance_id=i))
+        meta.append((i, -1, 0, 0))
+        for p in range(n_child):
+            e, old, new, _ = hs.instance_mutate(dict(L=8, J=J, live=None), A, i, cfg.seed, 99, p)
+            J2 = J.copy()
+            J2[e] = new
+            cands.append(dict(L=8, J=J2, live=None, instance_id=i))
+            meta.append((i, p, old, new))
+    print(f"network gain: scoring {len(cands)} instances by PT", flush=True)
+    ln, _ = hs.hardness_eval(cands, cfg.restarts, cfg.K, cfg.R, cfg.beta, cfg.swap_interval, cfg.s_max, cfg.seed)
+    ln = np.asarray(ln)
+    train = [k for k, m in enumerate(meta) if m[0] < n_train]
+    sur = hs.Surrogate(workloads.gnn_params(G.n_params(), P.gnn_fan_ins()))
+    for _ in range(12):
+        order = rng.permutation(len(train))
+        for a in range(0, len(order) - 31, 32):
+            b = [train[j] for j in order[a:a + 32]]
+            sur.train_step(ln[b], graphs=[(8, None, cands[k]["J"]) for k in b], lr=1e-3)
+    held = [k for k, m in enumerate(meta) if m[0] >= n_train]
+    pred = np.concatenate([sur.forward([(8, None, cands[k]["J"]) for k in held[a:a + 128]])
+                           for a in range(0, len(held), 128)])
+    pred = dict(zip(held, pred))
+    rho_net, rho_rand, rho_heur = [], [], []
+    for i in range(n_train, n_par):
+        kp = next(k for k, m in enumerate(meta) if m[0] == i and m[1] < 0)
+        kc = [k for k, m in enumerate(meta) if m[0] == i and m[1] >= 0]
+        true = ln[kc] - ln[kp]
+        rho_net.append(stats.spearmanr([pred[k] - pred[kp] for k in kc], true)[0])
+        rho_rand.append(stats.spearmanr(rng.permutation(n_child), true)[0])
+        rho_heur.append(stats.spearmanr([abs(meta[k][3]) - abs(meta[k][2]) for k in kc], true)[0])
+    net, rnd, heur = (float(np.nanmean(r)) for r in (rho_net, rho_rand, rho_heur))
+    se = float(np.nanstd(rho_net) / np.sqrt(len(rho_net)))
+    print(f"network gain: held-out proposal ranking, mean Spearman rho: network {net:.3f} (s.e. {se:.3f}), "
+          f"random {rnd:.3f}, |J| heuristic {heur:.3f}", flush=True)
+    assert net > 0.03, (net, rnd, heur)
