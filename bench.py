@@ -87,6 +87,8 @@ def parse():
                         "plain / surrogate-screened / random-screened instance search")
     p.add_argument("--pack", choices=["auto", "on", "off"], default="auto",
                    help="uneven workload: lane packing of instances of one size (auto: the tuner decides)")
+    p.add_argument("--tune-cache", default=None,
+                   help="uneven workload: JSON file caching the tuned launch plan by the batch's size classes")
     p.add_argument("--search-steps", type=int, default=20)
     p.add_argument("--search-chains", type=int, default=64)
     p.add_argument("--search-groups", type=int, default=4,
@@ -347,20 +349,21 @@ def uneven(args):
     sweeps = args.sweeps or cfg["sweeps"]
     live_per_sweep = sum(int(d["K"]) * int(d["R"]) * int(np.count_nonzero(d["live"])) for d in insts)
     # the tuner times the workgroup shapes of the plain plan (one instance per
-    # workgroup) and of the packed plan (instances of one size sharing lanes)
-    plans = {"off": [0], "on": [hs.HS_PACK_LANES], "auto": [0, hs.HS_PACK_LANES]}[args.pack]
+    # workgroup) and of the packed plan (instances of one size sharing lanes),
+    # cached by the batch's size classes
+    from paper_1605_03607_amd import tuning
     t0 = time.perf_counter()
-    tried = []
-    for flags in plans:
-        if args.block_waves:
-            tried.append((0.0, args.block_waves, flags))
-        else:
-            bw_f, us_f = hs.autotune(insts, cfg["seed"], swap_interval=cfg["swap_interval"], flags=flags,
-                                     trial_sweeps=200)
-            tried.append((us_f, bw_f, flags))
-    us, bw, flags = min(tried)
+    if args.block_waves or args.pack != "auto":
+        bw = args.block_waves or 16
+        flags = hs.HS_PACK_LANES if args.pack == "on" else 0
+        plan = {"tried": [], "cached": False, "us_per_sweep": None}
+    else:
+        bw, flags, plan = tuning.tuned_plan(insts, cfg["seed"], cfg["swap_interval"], cache_path=args.tune_cache)
+    us = plan.get("us_per_sweep")
+    tried = [(t["us_per_sweep"], t["block_waves"], hs.HS_PACK_LANES if t["packed"] else 0)
+             for t in plan.get("tried", [])]
     tune_s = time.perf_counter() - t0
-    print(f"# autotune: {tried} -> block_waves={bw}, flags={flags} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
+    print(f"# autotune: {plan} -> block_waves={bw}, flags={flags} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
     batch = hs.PTBatch(insts, cfg["seed"], swap_interval=cfg["swap_interval"], block_waves=bw, flags=flags)
     _, _, _, items, lane_slots = batch.launch_shape()
     graph = batch.graph(sweeps)
@@ -392,7 +395,7 @@ def uneven(args):
         "config": {"workload": cfg["name"], "instances": len(insts), "sweeps_per_step": sweeps,
                    "swap_interval": cfg["swap_interval"], "block_waves": bw,
                    "packed_lanes": bool(flags & hs.HS_PACK_LANES), "work_items": items,
-                   "autotune_us_per_sweep": us,
+                   "autotune_us_per_sweep": us, "autotune_cached": plan.get("cached"),
                    "autotune_tried": [{"us_per_sweep": t[0], "block_waves": t[1],
                                        "packed_lanes": bool(t[2] & hs.HS_PACK_LANES)} for t in tried],
                    "live_attempts_per_sweep": live_per_sweep,
