@@ -97,6 +97,12 @@ def parse():
                    help="screened arms: proposals per chain scored by PT after the screen")
     p.add_argument("--search-log", default=None,
                    help="search workloads: write every acceptance decision as a JSON line to this file")
+    p.add_argument("--validate", choices=["during", "after"], default="during",
+                   help="search workloads: re-score counted states on a stream of their own while the search "
+                        "runs (during), or after its last step")
+    p.add_argument("--hw-queues", type=int, default=8,
+                   help="search workloads: hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32); "
+                        "the chain groups and the validation stream each need one")
     p.add_argument("--tau-emcs", type=int, default=20000, help="EMCS of the --workload tau run")
     p.add_argument("--probe", action="store_true",
                    help="also measure instruction issue rates (libhsprobe.so)")
@@ -433,6 +439,37 @@ TTS_READING = ("ln TTS = ln(sweeps of all restarts / restarts whose minimum is t
                "workload description names")
 
 
+def _run_validated(args, S, run, seeds, bars, name):
+    """The timed steps of a search and the validation of its counted states:
+    during the search (a Validator on the stream after the groups' ones) or
+    after it.  Returns (search wall s, validation dict); the validated rate's
+    hour is the wall plus val["seconds"] (the wait for the last validation
+    launches, or the whole validation when it runs after the search)."""
+    t0 = time.perf_counter()
+    v = None
+    if args.validate == "during":
+        v = S.Validator(run.cfg, seeds, stream_index=args.search_groups)
+        run.attach(v)
+    run.run(args.search_steps, bars=bars, progress=_search_progress(name, args))
+    wall = time.perf_counter() - t0
+    print(f"# {name}: validating {len(run.hard_J)} counted states ({args.validate} the search)",
+          file=sys.stderr, flush=True)
+    val = v.finish(bars) if v is not None else S.validate(run, seeds, bars)
+    return wall, val
+
+
+def _validation_record(val, rule):
+    return {"h0_fresh_ln_tts": val["h0"], "states": val["states"], "restarts": val["restarts"],
+            "seconds": val["seconds"], "pt_sweeps": val["sweeps"], "pt_attempts": int(val["attempts"]),
+            "pt_device_ms": val["device_ms"], "overlapped_with_search": val["overlapped"], "rule": rule}
+
+
+def _chip_share(attempts, seconds):
+    """Spin-flip attempts x the reference op count over `seconds`, as a
+    fraction of the ALU peak."""
+    return attempts * A_OPS / seconds / PEAK_INT32_OPS if seconds > 0 else None
+
+
 def search(args):
     """Hard instances per hour of the instance search (Algorithm 1) on C8:
     plain chains, surrogate-screened chains and the random-screen ablation,
@@ -451,15 +488,12 @@ def search(args):
         run = S.GroupedSearch(cfg, seeds, groups=args.search_groups,
                               surrogate_params=params if mode == "surrogate" else None)
         t_init = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        run.run(args.search_steps, bars=tuple(bars.values()), progress=_search_progress(mode, args))
-        wall = time.perf_counter() - t0
+        wall, val = _run_validated(args, S, run, seeds, tuple(bars.values()), mode)
         hours = wall / 3600.0
         hard = {name: len(run.hard.get(b, set())) for name, b in bars.items()}
         _write_decisions(args, mode, run, "w" if mode == "plain" else "a")
-        print(f"# {mode}: validating {len(run.hard_J)} counted states", file=sys.stderr, flush=True)
-        val = S.validate(run, seeds, tuple(bars.values()))
-        v_hours = (wall + val["seconds"]) / 3600.0
+        v_wall = wall + val["seconds"]
+        v_hours = v_wall / 3600.0
         finite = np.isfinite(run.ln)
         arms[mode] = {
             "steps": args.search_steps, "seconds": wall, "s_per_step": wall / args.search_steps,
@@ -468,12 +502,12 @@ def search(args):
             "pt_device_ms": run.pt_device_ms, "pt_attempts": int(run.pt_attempts), "pt_calls": run.pt_calls,
             "validated_hard_instances": {name: val["counts"][b] for name, b in bars.items()},
             "validated_hard_instances_per_hour": {name: val["counts"][b] / v_hours for name, b in bars.items()},
-            "validation": {"h0_fresh_ln_tts": val["h0"], "states": val["states"], "restarts": val["restarts"],
-                           "seconds": val["seconds"], "pt_sweeps": val["sweeps"],
-                           "rule": "a counted state is re-scored with 64 restarts on streams disjoint from the "
-                                   "search's and kept if its fresh ln TTS >= H0' + bar (H0' = median fresh ln TTS "
-                                   "of the seeds) and its ground state is confirmed; the hour includes this "
-                                   "re-scoring"},
+            "validation": _validation_record(
+                val, "a counted state is re-scored with 64 restarts on streams disjoint from the search's and "
+                     "kept if its fresh ln TTS >= H0' + bar (H0' = median fresh ln TTS of the seeds) and its "
+                     "ground state is confirmed; the hour includes this re-scoring"),
+            "chip_share_search": _chip_share(run.pt_attempts, wall),
+            "chip_share_with_validation": _chip_share(run.pt_attempts + val["attempts"], v_wall),
             "hard_instances": hard,
             "hard_instances_per_hour": {k: v / hours for k, v in hard.items()},
             "final_median_ln_tts_finite": float(np.median(run.ln[finite])) if finite.any() else None,
@@ -493,7 +527,10 @@ def search(args):
         "config": {"workload": f"instance search, {args.search_chains} C8 chains, +-1 seeds, "
                                "mutations in +-1..+-7, 32 restarts K32 R2, T_s 0.5",
                    "bounded_steps": args.search_steps, "chain_groups": args.search_groups,
-                   "screen": f"16 proposals, top {args.search_top} scored by PT"},
+                   "screen": f"16 proposals, top {args.search_top} scored by PT",
+                   "validation": args.validate, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
+        "chip_share_note": "chip shares are spin-flip attempts x 22 ops over the wall, as a fraction of the "
+                           "ALU peak; the sweep kernel's own full-batch fraction (C8 benchmark) bounds them",
         "surrogate_over_plain": (rate("surrogate") / rate("plain")) if rate("plain") > 0 else None,
         "surrogate_over_plain_unvalidated": (raw("surrogate") / raw("plain")) if raw("plain") > 0 else None,
         "random_over_plain": (rate("random") / rate("plain")) if rate("plain") > 0 else None,
@@ -525,12 +562,9 @@ def search_reverse(args):
     cfg = S.SearchConfig(mode="plain", chains=args.search_chains, direction=-1, alphabet=S.ALPHABET_PM1)
     run = S.GroupedSearch(cfg, seeds, groups=args.search_groups)
     h0 = run.h0
-    t0 = time.perf_counter()
-    run.run(args.search_steps, bars=tuple(bars.values()), progress=_search_progress("reverse", args))
-    wall = time.perf_counter() - t0
+    wall, val = _run_validated(args, S, run, seeds, tuple(bars.values()), "reverse")
     easy = {name: len(run.hard.get(b, set())) for name, b in bars.items()}
     _write_decisions(args, "reverse", run, "w")
-    val = S.validate(run, seeds, tuple(bars.values()))
     v_easy = {name: val["counts"][b] for name, b in bars.items()}
     med = float(np.median(run.ln))
     out = {
@@ -540,15 +574,20 @@ def search_reverse(args):
         "tts_reading": TTS_READING,
         "unvalidated_easy_instances_per_hour": easy["ln3"] / (wall / 3600.0),
         "validated_easy_instances": v_easy,
-        "validation": {"h0_fresh_ln_tts": val["h0"], "states": val["states"], "restarts": val["restarts"],
-                       "seconds": val["seconds"]},
+        "validation": _validation_record(
+            val, "a counted state is re-scored with 64 restarts on streams disjoint from the search's and kept "
+                 "if its fresh ln TTS <= H0' - bar (H0' = median fresh ln TTS of the seeds) and its ground state "
+                 "is confirmed; the hour includes this re-scoring"),
+        "chip_share_search": _chip_share(run.pt_attempts, wall),
+        "chip_share_with_validation": _chip_share(run.pt_attempts + val["attempts"], wall + val["seconds"]),
         "n_gpus": 1, "steps": args.search_steps, "warmup": 0,
         "ms_per_step": wall * 1e3 / args.search_steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32 (PT)", "data": "synthetic",
         "config": {"workload": f"reversed instance search, {args.search_chains} C8 chains, +-1 seeds, "
                                "sign-flip mutations (J stays +-1), 32 restarts K32 R2, T_s 0.5",
-                   "bounded_steps": args.search_steps, "chain_groups": args.search_groups},
+                   "bounded_steps": args.search_steps, "chain_groups": args.search_groups,
+                   "validation": args.validate, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
         "easy_instances": easy, "h0_ln_tts": h0, "final_median_ln_tts": med,
         "median_drop_ln": h0 - med, "accepted": run.accepted, "pt_sweeps": int(run.pt_sweeps),
         "roofline": pt_roofline(run.pt_attempts, run.pt_device_ms, run.pt_calls,
@@ -656,7 +695,8 @@ def lao(args):
         "dtype": "int32 (PT)", "data": "synthetic",
         "config": {"workload": f"LAO, {args.search_chains} planted C8 chains, 350 loops (weights 1..5, "
                                "P(4-cycle) 0.1), 32 restarts K32 R2, T_s 0.5",
-                   "bounded_steps": args.search_steps, "chain_groups": args.search_groups},
+                   "bounded_steps": args.search_steps, "chain_groups": args.search_groups,
+                   "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
         "ratio_median": float(np.median(ratio)), "ratio_max": float(np.max(ratio)),
         "initial_mean_ln_tts": float(np.mean(run.ln0)), "final_mean_ln_tts": float(np.mean(run.ln)),
         "accepted": run.accepted, "scored": run.scored, "pt_ground_state_equals_planted": run.gs_found,
@@ -863,6 +903,13 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload in ("search", "search-reverse", "lao"):
+        if not 1 <= args.hw_queues <= 32:
+            print(json.dumps({"error": "--hw-queues must be in 1..32"}))
+            sys.exit(2)
+        # read by the HIP runtime when it starts, which is after this point
+        # (nothing has touched the GPU yet)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.workload == "uneven":
         uneven(args)
         return

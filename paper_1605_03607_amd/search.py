@@ -38,6 +38,7 @@ with it its screen, depends on the order in which groups finish.
 """
 import hashlib
 import math
+import queue
 import threading
 import time
 
@@ -143,6 +144,7 @@ class Search:
         self.hard = {}
         self.hard_J = {}  # couplings of every counted state, by key
         self.decisions = []
+        self.on_count = None  # called as on_count(key, J) once per newly counted state
 
     @property
     def gnn_seconds(self):
@@ -251,7 +253,10 @@ class Search:
                     if d * (y - self.h0) >= b:
                         k = _key(J2)
                         self.hard.setdefault(b, set()).add(k)
-                        self.hard_J.setdefault(k, J2)
+                        if k not in self.hard_J:
+                            self.hard_J[k] = J2
+                            if self.on_count is not None:
+                                self.on_count(k, J2)
         self._train()
         self.step += 1
 
@@ -346,6 +351,12 @@ class GroupedSearch:
 
         _in_groups(len(self.groups), walk)
 
+    def attach(self, validator):
+        """Hand every newly counted state of every group to validator.submit
+        (a Validator re-scoring them while the search runs)."""
+        for g in self.groups:
+            g.on_count = validator.submit
+
     @property
     def ln(self):
         return np.concatenate([g.ln for g in self.groups])
@@ -421,36 +432,151 @@ def validation_seed(cfg):
     return (int(cfg.seed) ^ VALIDATION_SEED_XOR) & 0xFFFFFFFF
 
 
+def validation_id(key):
+    """instance_id of a counted state in its validation run, from the key of
+    its couplings: the same whichever order states are counted or validated
+    in, and with the top bit set, so that no state shares the ids 0..n-1 of
+    the n seeds."""
+    return 0x80000000 | (int(key[:8], 16) & 0x7FFFFFFF)
+
+
+def _fresh_scores(cands, c, restarts, seed_v):
+    """hardness_eval of validation candidates on the current stream: (ln,
+    confirmed, sweeps, spin-flip attempts, device ms)."""
+    import torch
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    y, det = hardness_eval(cands, restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, seed_v)
+    end.record()
+    end.synchronize()
+    sweeps = sum(int(dd["sweeps_total"]) for dd in det)
+    return ([float(v) for v in y], [bool(dd["confirmed"]) for dd in det], sweeps,
+            sweeps * c.K * c.R * 8 * c.L * c.L, start.elapsed_time(end))
+
+
+def _tally(h0v, fresh, bars, direction):
+    """Validated count per bar: states whose fresh score is confirmed and
+    clears H0' + bar (below H0' - bar for the reversed search)."""
+    return {b: sum(1 for y, ok in fresh.values() if ok and direction * (y - h0v) >= b) for b in bars}
+
+
 def validate(run, seeds, bars, restarts=VALIDATION_RESTARTS, chunk=256):
     """Re-scores the seed instances and every counted state of `run` (a
-    Search or GroupedSearch) with independent restart streams.  A state is
-    validated at bar b when its fresh ln TTS clears H0' + b (H0' = median
-    fresh ln TTS of the seeds; below H0' - b for the reversed search) and its
-    ground state is confirmed.  Returns a dict with H0', the validated counts
-    per bar, the fresh scores and the seconds spent."""
+    Search or GroupedSearch) with independent restart streams, after the
+    search.  A state is validated at bar b when its fresh ln TTS clears
+    H0' + b (H0' = median fresh ln TTS of the seeds; below H0' - b for the
+    reversed search) and its ground state is confirmed.  Returns a dict with
+    H0', the validated counts per bar, the fresh scores and the seconds
+    spent."""
     c = run.cfg
     states = run.hard_J
     keys = sorted(states)
     cands = [dict(L=c.L, J=np.asarray(J, np.int8), live=None, instance_id=i) for i, J in enumerate(seeds)]
-    cands += [dict(L=c.L, J=states[k], live=None, instance_id=len(seeds) + i) for i, k in enumerate(keys)]
+    cands += [dict(L=c.L, J=states[k], live=None, instance_id=validation_id(k)) for k in keys]
     seed_v = validation_seed(c)
     t0 = time.perf_counter()
-    ln, conf, sweeps = [], [], 0
+    ln, conf, sweeps, attempts, ms = [], [], 0, 0, 0.0
     for a in range(0, len(cands), chunk):
-        part = cands[a:a + chunk]
-        y, det = hardness_eval(part, restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, seed_v)
-        ln += [float(v) for v in y]
-        conf += [bool(dd["confirmed"]) for dd in det]
-        sweeps += sum(int(dd["sweeps_total"]) for dd in det)
+        y, ok, sw, att, t = _fresh_scores(cands[a:a + chunk], c, restarts, seed_v)
+        ln += y
+        conf += ok
+        sweeps += sw
+        attempts += att
+        ms += t
     seconds = time.perf_counter() - t0
     h0v = float(np.median(ln[:len(seeds)]))
     fresh = {k: (ln[len(seeds) + i], conf[len(seeds) + i]) for i, k in enumerate(keys)}
-    d = c.direction
-    counts = {}
-    for b in bars:
-        counts[b] = sum(1 for k in keys if fresh[k][1] and d * (fresh[k][0] - h0v) >= b)
-    return dict(h0=h0v, counts=counts, fresh=fresh, seconds=seconds, sweeps=sweeps, restarts=restarts,
-                seed=seed_v, states=len(keys))
+    return dict(h0=h0v, counts=_tally(h0v, fresh, bars, c.direction), fresh=fresh, seconds=seconds,
+                sweeps=sweeps, attempts=attempts, device_ms=ms, restarts=restarts, seed=seed_v,
+                states=len(keys), overlapped=False)
+
+
+class Validator:
+    """validate() while the search runs.  A host thread on a stream of its
+    own scores the seeds first, then takes the states the search counts as
+    they arrive (GroupedSearch.attach or Search.on_count hand them over) and
+    scores everything waiting, up to `chunk` states, in one hardness_eval
+    call.  Its launches fill the chip while the search's launches wait for
+    their slowest restarts.  Every state keeps the instance id validate()
+    gives it, and a candidate's score does not depend on the launch it
+    shares, so finish() returns what validate() returns for the same states,
+    with `seconds` the time finish() waited for the last launches."""
+
+    def __init__(self, cfg, seeds, restarts=VALIDATION_RESTARTS, chunk=256, stream_index=0):
+        self.cfg = cfg
+        self.restarts = restarts
+        self.chunk = chunk
+        self.seed = validation_seed(cfg)
+        self._seeds = [np.array(J, np.int8) for J in seeds]
+        self._queue = queue.Queue()
+        self._seen = set()
+        self._lock = threading.Lock()
+        self._error = None
+        self.fresh = {}
+        self.h0 = None
+        self.sweeps = 0
+        self.attempts = 0
+        self.device_ms = 0.0
+        self.calls = 0
+        self._stream = _group_stream(stream_index)  # made here: the list of streams is not thread-safe
+        self._thread = threading.Thread(target=self._run, daemon=True)
+        self._thread.start()
+
+    def submit(self, key, J):
+        """Queue one counted state (called from any search thread)."""
+        with self._lock:
+            if key in self._seen:
+                return
+            self._seen.add(key)
+        self._queue.put((key, np.array(J, np.int8)))
+
+    def _score(self, cands):
+        y, ok, sw, att, ms = _fresh_scores(cands, self.cfg, self.restarts, self.seed)
+        self.sweeps += sw
+        self.attempts += att
+        self.device_ms += ms
+        self.calls += 1
+        return y, ok
+
+    def _run(self):
+        stream, current = self._stream
+        c = self.cfg
+        try:
+            with current:
+                y, _ = self._score([dict(L=c.L, J=J, live=None, instance_id=i) for i, J in enumerate(self._seeds)])
+                self.h0 = float(np.median(y))
+                done = False
+                while not done:
+                    batch = [self._queue.get()]
+                    while len(batch) < self.chunk and batch[-1] is not None:
+                        try:
+                            batch.append(self._queue.get_nowait())
+                        except queue.Empty:
+                            break
+                    if batch[-1] is None:
+                        batch.pop()
+                        done = True
+                    if batch:
+                        y, ok = self._score([dict(L=c.L, J=J, live=None, instance_id=validation_id(k))
+                                             for k, J in batch])
+                        for (k, _), v, conf in zip(batch, y, ok):
+                            self.fresh[k] = (v, conf)
+            stream.synchronize()
+        except BaseException as e:  # noqa: BLE001 - raised by finish()
+            self._error = e
+
+    def finish(self, bars):
+        """Waits for every queued state and returns validate()'s dict."""
+        t0 = time.perf_counter()
+        self._queue.put(None)
+        self._thread.join()
+        seconds = time.perf_counter() - t0
+        if self._error is not None:
+            raise self._error
+        return dict(h0=self.h0, counts=_tally(self.h0, self.fresh, bars, self.cfg.direction),
+                    fresh=dict(self.fresh), seconds=seconds, sweeps=self.sweeps, attempts=self.attempts,
+                    device_ms=self.device_ms, restarts=self.restarts, seed=self.seed, states=len(self.fresh),
+                    overlapped=True, calls=self.calls)
 
 
 class LaoSearch:

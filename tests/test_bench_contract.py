@@ -22,6 +22,15 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
 
 
+def test_hardware_queue_count_is_bounded():
+    """The search workloads set GPU_MAX_HW_QUEUES for their process; a count
+    outside 1..32 is refused before anything touches the GPU."""
+    for n in ("0", "33"):
+        p = _bench("--workload", "search", "--hw-queues", n)
+        assert p.returncode == 2
+        assert "1..32" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
+
+
 def test_every_workload_is_offered():
     p = _bench("--help")
     assert p.returncode == 0

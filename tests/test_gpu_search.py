@@ -165,3 +165,35 @@ def test_plain_search_replays_on_the_oracle(direction):
                 J, ln = J2, ln2
         assert np.array_equal(run.J[ch], J) and run.ln[ch] == ln
     assert sorted(want) == sorted(run.decisions)
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+def test_validation_during_the_search(direction):
+    """A Validator re-scoring counted states on its own stream while two
+    chain groups run: the search takes the decisions of a search without it,
+    the fresh scores and counts equal validate()'s after the search, and a
+    counted state's fresh score equals the oracle's hardness on the
+    validation streams (its validation id and the validation seed)."""
+    hs = _gpu()
+    from paper_1605_03607_amd import search as S
+    chains, L, steps = 6, 3, 4
+    cfg = S.SearchConfig(mode="plain", chains=chains, L=L, restarts=4, K=8, R=2, s_max=3000, t_s=5.0,
+                         direction=direction, alphabet=S.ALPHABET_PM1 if direction < 0 else S.ALPHABET_PM7)
+    seeds = [workloads.couplings(L, "pm1", 89, c) for c in range(chains)]
+    bars = (math.log(1.1),)
+    bare = S.GroupedSearch(cfg, seeds, groups=2)
+    bare.run(steps, bars=bars)
+    run = S.GroupedSearch(cfg, seeds, groups=2)
+    v = S.Validator(cfg, seeds, restarts=8, chunk=4, stream_index=2)
+    run.attach(v)
+    run.run(steps, bars=bars)
+    got = v.finish(bars)
+    assert run.decisions == bare.decisions and run.hard == bare.hard
+    assert got["states"] == len(run.hard_J) > 0
+    want = S.validate(run, seeds, bars, restarts=8)
+    assert got["h0"] == want["h0"] and got["fresh"] == want["fresh"] and got["counts"] == want["counts"]
+    k = sorted(run.hard_J)[0]
+    print(f"validation on the oracle: state {k[:8]} (direction {direction})", flush=True)
+    o = oracle.hardness_eval(L, None, run.hard_J[k], S.validation_id(k), S.validation_seed(cfg), 8, cfg.K, cfg.R,
+                             cfg.beta, cfg.swap_interval, cfg.s_max)
+    assert got["fresh"][k] == (o["ln_tts"], o["confirmed"])

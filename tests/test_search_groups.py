@@ -39,6 +39,12 @@ def S(monkeypatch):
         ln, det = search.hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
         return ln, det, 0.0, 0
     monkeypatch.setattr(search, "_timed_hardness", untimed)
+
+    def fresh_untimed(cands, c, restarts, seed_v):  # the validation scorer without device events
+        ln, det = search.hardness_eval(cands, restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, seed_v)
+        return ([float(v) for v in ln], [bool(d["confirmed"]) for d in det],
+                sum(d["sweeps_total"] for d in det), 0, 0.0)
+    monkeypatch.setattr(search, "_fresh_scores", fresh_untimed)
     return search
 
 
@@ -244,12 +250,49 @@ def test_validation_uses_restart_streams_disjoint_from_the_search(S, monkeypatch
     h0v = float(np.median(fresh))
     assert v["h0"] == h0v
     keys = sorted(run.hard_J)
+    ids = [S.validation_id(k) for k in keys]
+    assert all(i >= 2**31 for i in ids) and len(set(ids)) == len(ids)
     for b in bars:
         want = 0
-        for i, k in enumerate(keys):
-            y = _fake_eval([dict(J=run.hard_J[k], instance_id=len(seeds) + i)], 0, 0, 0, 0, 0, 0, 0)[0][0]
+        for k in keys:
+            y = _fake_eval([dict(J=run.hard_J[k], instance_id=S.validation_id(k))], 0, 0, 0, 0, 0, 0, 0)[0][0]
             want += int(y - h0v >= b)
         assert v["counts"][b] == want
+
+
+@pytest.mark.parametrize("groups", [1, 3])
+def test_validation_during_the_search_equals_validation_after_it(S, groups):
+    """A Validator attached to the search re-scores each counted state as it
+    is counted, on its own thread, in launches of whatever is waiting; it
+    returns validate()'s H0', fresh scores and counts, and the search's
+    decisions are those of a search without it."""
+    cfg = S.SearchConfig(mode="random", chains=6, L=2, proposals=5, top=2, t_s=5.0)
+    seeds = [workloads.couplings(2, "pm1", 53, c) for c in range(6)]
+    bars = (math.log(1.1), math.log(1.5))
+    bare = S.GroupedSearch(cfg, seeds, groups=groups)
+    bare.run(6, bars=bars)
+    run = S.GroupedSearch(cfg, seeds, groups=groups)
+    val = S.Validator(cfg, seeds, chunk=3, stream_index=groups)
+    run.attach(val)
+    run.run(6, bars=bars)
+    got = val.finish(bars)
+    assert run.decisions == bare.decisions and run.hard == bare.hard
+    want = S.validate(run, seeds, bars)
+    assert got["overlapped"] and not want["overlapped"]
+    assert got["h0"] == want["h0"] and got["fresh"] == want["fresh"] and got["counts"] == want["counts"]
+    assert got["states"] == len(run.hard_J) > 3 and got["calls"] >= 2
+
+
+def test_validator_failure_reaches_finish(S, monkeypatch):
+    cfg = S.SearchConfig(mode="plain", chains=4, L=2, t_s=5.0)
+    seeds = [workloads.couplings(2, "pm1", 59, c) for c in range(4)]
+
+    def boom(*a, **k):
+        raise RuntimeError("validation launch failed")
+    monkeypatch.setattr(S, "_fresh_scores", boom)
+    val = S.Validator(cfg, seeds)
+    with pytest.raises(RuntimeError, match="validation launch failed"):
+        val.finish((math.log(1.1),))
 
 
 def test_checkpoint_keeps_the_counted_couplings(S, tmp_path):
