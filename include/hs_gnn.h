@@ -17,6 +17,7 @@
  *     h_v <- relu(W_h [h_v; sum of m_e over edges e into v] + b_h)
  *   y_hat = w_out . mean over live v of h_v + b_out      (predicts ln TTS)
  *   loss = mean over graphs with a finite label of (y_hat - label)^2
+ *          (gnn_train_step_ranked adds child-against-parent differences)
  *
  * Parameters: one float32 vector of gnn_param_count() entries, blocks in the
  * order W_en [64][5], b_en, W_ee [64][4], b_ee, then per layer W_m [64][192],
@@ -83,6 +84,21 @@ typedef struct hs_adam {
 int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labels, void *workspace,
                    size_t workspace_bytes, float *y_hat, float *loss, float *grad,
                    const hs_adam *adam, void *stream);
+
+/* gnn_train_step with the ranked loss, for ranking proposed mutations
+ * against the instance they were made from (the screen of the instance
+ * search, Algorithm 1, Sec. II.A, orders a parent's one-coupler children):
+ *   loss = mean over pairs of ((y_hat_g - y_hat_p) - (label_g - label_p))^2
+ *          + w_abs * (the loss of gnn_train_step)
+ * where graph g pairs with p = ref[g] when 0 <= p < n_graphs, p != g and
+ * both labels are finite.  ref: device int32 [n_graphs] (-1 = no parent).
+ * With common random numbers for a parent and its children the pair
+ * differences carry far less noise than the labels.  w_abs >= 0.
+ * HS_EINVAL for a NULL ref or a negative or non-finite w_abs; otherwise as
+ * gnn_train_step.  Asynchronous. */
+int gnn_train_step_ranked(float *params, int32_t n_graphs, int32_t L, const float *labels, const int32_t *ref,
+                          float w_abs, void *workspace, size_t workspace_bytes, float *y_hat, float *loss,
+                          float *grad, const hs_adam *adam, void *stream);
 
 #ifdef __cplusplus
 }

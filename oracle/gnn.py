@@ -17,6 +17,11 @@ Network (width D = 64, three layers, ReLU):
             h_v <- relu(W_h [h_v; sum_{e in in(v)} m_e] + b_h)
   y_hat = w . mean_{live v} h_v + b_out
 Loss: mean over graphs with a finite label of (y_hat - y)^2 (y = ln TTS).
+Ranked loss (a child instance against its parent, one coupler apart): with
+ref[g] the index of graph g's parent in the batch (-1: none),
+  mean over pairs (g, p = ref[g]) with p in range, p != g and both labels
+  finite of ((y_hat_g - y_hat_p) - (y_g - y_p))^2  +  w_abs * (the loss above)
+so that the network learns the change of ln TTS one mutation makes.
 Optimiser: Adam (Kingma and Ba, ICLR 2015) with bias correction.
 
 With bf16=True every value the GPU kernels hold in bfloat16 is rounded to
@@ -137,18 +142,32 @@ def forward(theta, B, bf=False):
     return y, cache
 
 
-def loss_and_grad(theta, B, labels, bf=False):
+def loss_and_grad(theta, B, labels, bf=False, ref=None, w_abs=1.0):
     """(loss, gradient (flat, like theta), y_hat); labels that are not
-    finite are left out of the mean."""
+    finite are left out of the mean.  With ref, the ranked loss (module
+    docstring) with weight w_abs on the plain term."""
     theta = np.asarray(theta, np.float64)
     P = unpack(theta)
     y, c = forward(theta, B, bf)
     G, N = B["G"], B["N"]
+    labels = np.asarray(labels, np.float64)
     ok = np.isfinite(labels)
     nv = max(1, int(ok.sum()))
     diff = np.where(ok, y - np.where(ok, labels, 0.0), 0.0)
     loss = float((diff ** 2).sum() / nv)
     dy = 2.0 * diff / nv
+    if ref is not None:
+        ref = [int(r) for r in ref]
+        pairs = [(g, ref[g]) for g in range(G) if 0 <= ref[g] < G and ref[g] != g and ok[g] and ok[ref[g]]]
+        npair = max(1, len(pairs))
+        loss *= w_abs
+        dy = dy * w_abs
+        for g, p_ in pairs:
+            d = (y[g] - y[p_]) - (labels[g] - labels[p_])
+            loss += d * d / npair
+            dy[g] += 2.0 * d / npair
+            dy[p_] -= 2.0 * d / npair
+        loss = float(loss)
     g = {k: np.zeros_like(v) for k, v in P.items()}
     g["w_out"] = dy @ c["mean"]
     g["b_out"][0] = dy.sum()

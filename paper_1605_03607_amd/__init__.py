@@ -134,6 +134,9 @@ def lib():
         L.gnn_train_step.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                      C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(hs_adam), C.c_void_p]
+        L.gnn_train_step_ranked.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_float,
+                                            C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.POINTER(hs_adam), C.c_void_p]
         _lib = L
     return _lib
 
@@ -164,7 +167,8 @@ def exported_symbols():
             "pt_autotune", "instance_mutate", "hs_rao_accept", "hardness_workspace_bytes",
             "hardness_eval", "gnn_param_count", "gnn_workspace_bytes", "gnn_prepare", "gnn_forward",
             "gnn_train_step", "pt_sweep_record", "walk_autocorr", "walk_tau", "lao_cycle_count", "lao_init",
-            "lao_move", "pt_capture", "overlap_analyze", "pt_launch_shape", "hardness_eval_static"]
+            "lao_move", "pt_capture", "overlap_analyze", "pt_launch_shape", "hardness_eval_static",
+            "gnn_train_step_ranked"]
 
 
 def _check(rc):
@@ -620,9 +624,13 @@ class Surrogate:
                                  self.ws.numel(), C.c_void_p(y.data_ptr()), _stream_ptr(self.stream)))
         return y.cpu().numpy()
 
-    def train_step(self, labels, graphs=None, lr=1e-3, update=True, betas=(0.9, 0.999), eps=1e-8):
+    def train_step(self, labels, graphs=None, lr=1e-3, update=True, betas=(0.9, 0.999), eps=1e-8, ref=None,
+                   w_abs=1.0):
         """One step on the prepared (or given) batch: (loss, y_hat); the
-        gradient stays in self.grad.  update=False leaves the parameters."""
+        gradient stays in self.grad.  update=False leaves the parameters.
+        With ref (the index of each graph's parent in the batch, -1 for
+        none) the step takes the ranked loss (gnn_train_step_ranked) with
+        weight w_abs on the plain term."""
         torch = self.torch
         if graphs is not None:
             self.prepare(graphs)
@@ -633,8 +641,18 @@ class Surrogate:
         if update:
             self.step += 1
             adam = hs_adam(lr, betas[0], betas[1], eps, self.step, self.m.data_ptr(), self.v.data_ptr())
-        _check(lib().gnn_train_step(C.c_void_p(self.params.data_ptr()), G, L, C.c_void_p(lab.data_ptr()),
-                                    C.c_void_p(self.ws.data_ptr()), self.ws.numel(), C.c_void_p(y.data_ptr()),
-                                    C.c_void_p(self.loss.data_ptr()), C.c_void_p(self.grad.data_ptr()),
-                                    None if adam is None else C.byref(adam), _stream_ptr(self.stream)))
+        tail = (C.c_void_p(self.ws.data_ptr()), self.ws.numel(), C.c_void_p(y.data_ptr()),
+                C.c_void_p(self.loss.data_ptr()), C.c_void_p(self.grad.data_ptr()),
+                None if adam is None else C.byref(adam), _stream_ptr(self.stream))
+        if ref is None:
+            _check(lib().gnn_train_step(C.c_void_p(self.params.data_ptr()), G, L, C.c_void_p(lab.data_ptr()),
+                                        *tail))
+        else:
+            r = np.ascontiguousarray(ref, np.int32)
+            if r.shape != (G,):
+                raise ValueError("one parent index per graph")
+            rd = torch.from_numpy(r).to(self.params.device)
+            _check(lib().gnn_train_step_ranked(C.c_void_p(self.params.data_ptr()), G, L,
+                                               C.c_void_p(lab.data_ptr()), C.c_void_p(rd.data_ptr()),
+                                               float(w_abs), *tail))
         return float(self.loss.item()), y.cpu().numpy()

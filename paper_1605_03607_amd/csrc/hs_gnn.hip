@@ -347,6 +347,61 @@ __global__ void k_loss(const float *y, const float *labels, const float *mean, i
     }
 }
 
+// The ranked loss (a child graph against its parent ref[g], plus w_abs times
+// the plain loss), d loss / d y_hat and the readout-parameter gradient (one
+// workgroup of 64).  A pair term needs 0 <= ref[g] < G, ref[g] != g and both
+// labels finite; each thread sums its own graphs' terms in graph order, so
+// the result does not depend on thread timing.
+__global__ void k_loss_ranked(const float *y, const float *labels, const int32_t *ref, float w_abs,
+                              const float *mean, int G, float *dy, float *loss, float *grad)
+{
+    const int t = threadIdx.x;
+    __shared__ int nvalid, npair;
+    auto paired = [&](int g) {
+        const int p = ref[g];
+        return p >= 0 && p < G && p != g && isfinite(labels[g]) && isfinite(labels[p]);
+    };
+    if (t == 0) {
+        int c = 0, q = 0;
+        for (int g = 0; g < G; ++g) {
+            c += isfinite(labels[g]) ? 1 : 0;
+            q += paired(g) ? 1 : 0;
+        }
+        nvalid = c > 0 ? c : 1;
+        npair = q > 0 ? q : 1;
+    }
+    __syncthreads();
+    const float inv = 1.f / float(nvalid), invp = 1.f / float(npair);
+    auto pair_d = [&](int g) { return (y[g] - y[ref[g]]) - (labels[g] - labels[ref[g]]); };
+    for (int g = t; g < G; g += blockDim.x) {
+        float v = isfinite(labels[g]) ? w_abs * 2.f * (y[g] - labels[g]) * inv : 0.f;
+        if (paired(g)) v += 2.f * pair_d(g) * invp;
+        for (int h = 0; h < G; ++h)
+            if (ref[h] == g && paired(h)) v -= 2.f * pair_d(h) * invp;
+        dy[g] = v;
+    }
+    __syncthreads();
+    float gw = 0.f;
+    for (int g = 0; g < G; ++g) gw += dy[g] * mean[g * D + t];
+    grad[kWout + t] = gw;
+    if (t == 0) {
+        float l = 0.f, lp = 0.f, gb = 0.f;
+        for (int g = 0; g < G; ++g) {
+            if (isfinite(labels[g])) {
+                const float df = y[g] - labels[g];
+                l += df * df;
+            }
+            if (paired(g)) {
+                const float d = pair_d(g);
+                lp += d * d;
+            }
+            gb += dy[g];
+        }
+        *loss = w_abs * l * inv + lp * invp;
+        grad[kBout] = gb;
+    }
+}
+
 __global__ void k_readout_bwd(const float *dy, const float *P, const float *live, const float *nlive, float *dH,
                               int nn, int n)
 {
@@ -551,7 +606,7 @@ bool make_layout(int G, int L, Layout &o)
     return true;
 }
 
-int hip_err(hipError_t e, const char *what) { return fail(HS_EHIP, std::string(what) + ": " + hipGetErrorString(e)); }
+int hip_err(hipError_t e, const std::string &what) { return fail(HS_EHIP, what + ": " + hipGetErrorString(e)); }
 
 struct Bufs {
     float *xn, *xe, *live, *nlive, *mean, *y, *dy, *dXe[2], *dXn, *dH, *bpart, *rpart, *epart, *Zm[kLayers], *Zh[kLayers];
@@ -737,16 +792,22 @@ int gnn_forward(const float *params, int32_t n_graphs, int32_t L, void *workspac
     return e == hipSuccess ? HS_OK : hip_err(e, "gnn_forward: copy");
 }
 
-int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labels, void *workspace,
-                   size_t workspace_bytes, float *y_hat, float *loss, float *grad, const hs_adam *adam,
-                   void *stream)
+}  // extern "C"
+
+namespace {
+
+// Forward pass, loss (plain, or ranked when ref is not NULL), backward pass
+// and the optional Adam update of one training step.
+int train_step(const char *who, float *params, int32_t n_graphs, int32_t L, const float *labels,
+               const int32_t *ref, float w_abs, void *workspace, size_t workspace_bytes, float *y_hat, float *loss,
+               float *grad, const hs_adam *adam, void *stream)
 {
     if (params == nullptr || labels == nullptr || workspace == nullptr || loss == nullptr || grad == nullptr)
-        return fail(HS_EINVAL, "gnn_train_step: NULL argument");
+        return fail(HS_EINVAL, std::string(who) + ": NULL argument");
     if (adam && (adam->m == nullptr || adam->v == nullptr || adam->step < 1))
-        return fail(HS_EINVAL, "gnn_train_step: bad Adam state");
+        return fail(HS_EINVAL, std::string(who) + ": bad Adam state");
     Layout o;
-    int rc = check_ws(n_graphs, L, workspace_bytes, o, "gnn_train_step");
+    int rc = check_ws(n_graphs, L, workspace_bytes, o, who);
     if (rc) return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const Bufs v = views(o, workspace);
@@ -754,7 +815,11 @@ int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labe
     if (rc) return rc;
     const int ne = int(o.ne), nn = int(o.nn);
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(kParams, 256)), dim3(256), 0, st, grad, int64_t(kParams), 0.f);
-    hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, st, v.y, labels, v.mean, o.G, v.dy, loss, grad);
+    if (ref)
+        hipLaunchKernelGGL(k_loss_ranked, dim3(1), dim3(64), 0, st, v.y, labels, ref, w_abs, v.mean, o.G, v.dy,
+                           loss, grad);
+    else
+        hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, st, v.y, labels, v.mean, o.G, v.dy, loss, grad);
     hipLaunchKernelGGL(k_readout_bwd, dim3(blocks_for(o.nn * D, 256)), dim3(256), 0, st, v.dy, params, v.live,
                        v.nlive, v.dH, nn, o.N);
     const float *dXe_above = nullptr;
@@ -792,10 +857,10 @@ int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labe
                        int(o.nq), v.epart);
     hipLaunchKernelGGL(k_embed_sum, dim3(D, 2), dim3(256), 0, st, v.epart, kEmbBlocks, grad);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_err(e, "gnn_train_step: launch");
+    if (e != hipSuccess) return hip_err(e, std::string(who) + ": launch");
     if (y_hat) {
         e = hipMemcpyAsync(y_hat, v.y, size_t(o.G) * 4, hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return hip_err(e, "gnn_train_step: copy");
+        if (e != hipSuccess) return hip_err(e, std::string(who) + ": copy");
     }
     if (adam) {
         const double t = double(adam->step);
@@ -804,9 +869,31 @@ int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labe
         hipLaunchKernelGGL(k_adam, dim3(blocks_for(kParams, 256)), dim3(256), 0, st, params, grad, adam->m,
                            adam->v, kParams, adam->lr, adam->beta1, adam->beta2, adam->eps, c1, c2);
         e = hipGetLastError();
-        if (e != hipSuccess) return hip_err(e, "gnn_train_step: Adam");
+        if (e != hipSuccess) return hip_err(e, std::string(who) + ": Adam");
     }
     return HS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gnn_train_step(float *params, int32_t n_graphs, int32_t L, const float *labels, void *workspace,
+                   size_t workspace_bytes, float *y_hat, float *loss, float *grad, const hs_adam *adam,
+                   void *stream)
+{
+    return train_step("gnn_train_step", params, n_graphs, L, labels, nullptr, 1.f, workspace, workspace_bytes,
+                      y_hat, loss, grad, adam, stream);
+}
+
+int gnn_train_step_ranked(float *params, int32_t n_graphs, int32_t L, const float *labels, const int32_t *ref,
+                          float w_abs, void *workspace, size_t workspace_bytes, float *y_hat, float *loss,
+                          float *grad, const hs_adam *adam, void *stream)
+{
+    if (ref == nullptr) return fail(HS_EINVAL, "gnn_train_step_ranked: NULL ref");
+    if (!(w_abs >= 0.f) || !std::isfinite(w_abs)) return fail(HS_EINVAL, "gnn_train_step_ranked: w_abs");
+    return train_step("gnn_train_step_ranked", params, n_graphs, L, labels, ref, w_abs, workspace,
+                      workspace_bytes, y_hat, loss, grad, adam, stream);
 }
 
 }  // extern "C"

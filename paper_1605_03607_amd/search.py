@@ -74,7 +74,7 @@ class SearchConfig:
     def __init__(self, mode="plain", chains=64, L=8, restarts=32, K=32, R=2, beta=(0.1, 5.0),
                  swap_interval=1, s_max=100_000, t_s=0.5, seed=1605, proposals=16, top=2,
                  train_steps=32, train_batch=32, lr=3e-3, replay=4096, screen_chunk=128, direction=1,
-                 alphabet=ALPHABET_PM7):
+                 alphabet=ALPHABET_PM7, train_loss="ranked", w_abs=0.1):
         if direction not in (1, -1):
             raise ValueError("direction is +1 (harder) or -1 (easier)")
         self.mode = mode
@@ -87,6 +87,9 @@ class SearchConfig:
         self.top = 1 if mode == "plain" else top
         self.train_steps, self.train_batch, self.lr = train_steps, train_batch, lr
         self.replay, self.screen_chunk = replay, screen_chunk
+        if train_loss not in ("ranked", "plain"):
+            raise ValueError("train_loss is 'ranked' or 'plain'")
+        self.train_loss, self.w_abs = train_loss, float(w_abs)
 
 
 def _key(J):
@@ -95,25 +98,36 @@ def _key(J):
 
 class _Pool:
     """What the chain groups of one search share: the surrogate, the replay
-    buffer of PT-scored (J, ln TTS) pairs and the training draws."""
+    buffer of PT-scored (J, ln TTS) records and the training draws.  A
+    record of a scored proposal also keeps the instance it was made from and
+    that instance's score (the chain's current state, scored on the same
+    restart streams), for the ranked loss; a seed's record has none."""
 
     def __init__(self, cfg, surrogate_params):
         self.sur = Surrogate(surrogate_params) if cfg.mode == "surrogate" else None
         self.pairs_J, self.pairs_y = [], []
+        self.parent_J, self.parent_y = [], []  # None / nan for records without a parent
         self.rng = np.random.default_rng(cfg.seed + 77)
         self.lock = threading.Lock()
         self.gnn_seconds = 0.0
         self.replay = cfg.replay
 
-    def add(self, cands, ln):
+    def add(self, cands, ln, parents=None):
+        """parents: (J, ln TTS) of each candidate's parent, or None."""
         with self.lock:
-            for cd, y in zip(cands, ln):
+            for i, (cd, y) in enumerate(zip(cands, ln)):
                 if math.isfinite(y):
                     self.pairs_J.append(np.array(cd["J"], np.int8))
                     self.pairs_y.append(float(y))
+                    pj, py = parents[i] if parents is not None else (None, math.nan)
+                    ok = pj is not None and math.isfinite(py)
+                    self.parent_J.append(np.array(pj, np.int8) if ok else None)
+                    self.parent_y.append(float(py) if ok else math.nan)
             if len(self.pairs_J) > self.replay:
                 self.pairs_J = self.pairs_J[-self.replay:]
                 self.pairs_y = self.pairs_y[-self.replay:]
+                self.parent_J = self.parent_J[-self.replay:]
+                self.parent_y = self.parent_y[-self.replay:]
 
 
 class Search:
@@ -157,8 +171,9 @@ class Search:
     def _seed_cands(self):
         return [dict(L=self.cfg.L, J=J, live=None, instance_id=i) for i, J in zip(self.ids, self.J)]
 
-    def _score(self, cands, keep=True):
-        """ln TTS of the candidates; keep=True adds them to the replay buffer."""
+    def _score(self, cands, keep=True, parents=None):
+        """ln TTS of the candidates; keep=True adds them (with their parents)
+        to the replay buffer."""
         c = self.cfg
         t0 = time.perf_counter()
         ln, det, ms, att = _timed_hardness(cands, c)
@@ -168,7 +183,7 @@ class Search:
         self.pt_attempts += att
         self.pt_calls += 1
         if keep:
-            self.pool.add(cands, ln)
+            self.pool.add(cands, ln, parents)
         return ln
 
     def _proposals(self, chain):
@@ -201,13 +216,29 @@ class Search:
         if pool.sur is None:
             return
         with pool.lock:
-            if len(pool.pairs_J) < c.train_batch:
-                return
             t0 = time.perf_counter()
-            for _ in range(self.train_steps):
-                idx = pool.rng.choice(len(pool.pairs_J), size=c.train_batch, replace=False)
-                pool.sur.train_step(np.array([pool.pairs_y[i] for i in idx]),
-                                    graphs=[(c.L, None, pool.pairs_J[i]) for i in idx], lr=c.lr)
+            if c.train_loss == "ranked":
+                # batches of train_batch / 2 (parent, proposal) pairs: the
+                # network learns how much one mutation changes ln TTS
+                linked = [i for i, pj in enumerate(pool.parent_J) if pj is not None]
+                half = c.train_batch // 2
+                if len(linked) < half:
+                    return
+                ref = np.array([-1 if k % 2 == 0 else k - 1 for k in range(2 * half)], np.int32)  # parent, child
+                for _ in range(self.train_steps):
+                    idx = pool.rng.choice(len(linked), size=half, replace=False)
+                    graphs, labels = [], []
+                    for i in (linked[j] for j in idx):
+                        graphs += [(c.L, None, pool.parent_J[i]), (c.L, None, pool.pairs_J[i])]
+                        labels += [pool.parent_y[i], pool.pairs_y[i]]
+                    pool.sur.train_step(np.array(labels), graphs=graphs, lr=c.lr, ref=ref, w_abs=c.w_abs)
+            else:
+                if len(pool.pairs_J) < c.train_batch:
+                    return
+                for _ in range(self.train_steps):
+                    idx = pool.rng.choice(len(pool.pairs_J), size=c.train_batch, replace=False)
+                    pool.sur.train_step(np.array([pool.pairs_y[i] for i in idx]),
+                                        graphs=[(c.L, None, pool.pairs_J[i]) for i in idx], lr=c.lr)
             pool.gnn_seconds += time.perf_counter() - t0
 
     def _random_screen(self, chain):
@@ -228,13 +259,14 @@ class Search:
             chosen = [sorted(np.argsort(-pred[ch], kind="stable")[:c.top].tolist()) for ch in range(n)]
         else:
             chosen = [self._random_screen(ch) for ch in range(n)]
-        cands, owner = [], []
+        cands, owner, parents = [], [], []
         for ch in range(n):
             for p in chosen[ch]:
                 J2, _, _ = props[ch][p]
                 cands.append(dict(L=c.L, J=J2, live=None, instance_id=self.ids[ch]))
                 owner.append((ch, p))
-        ln = self._score(cands)
+                parents.append((self.J[ch], float(self.ln[ch])))
+        ln = self._score(cands, parents=parents)
         best = {}
         d = c.direction
         for (ch, p), y in zip(owner, ln):
@@ -715,9 +747,9 @@ class GroupedLao:
 # objects, written to a temporary name and renamed, so a process killed while
 # saving leaves the previous checkpoint intact.
 
-_CKPT_VERSION = 2
+_CKPT_VERSION = 3
 _CFG_KEYS = ("mode", "direction", "chains", "L", "restarts", "K", "R", "swap_interval", "s_max", "t_s", "seed",
-             "proposals", "top", "train_steps", "train_batch", "lr", "replay")
+             "proposals", "top", "train_steps", "train_batch", "lr", "replay", "train_loss", "w_abs")
 
 
 def _cfg_record(cfg):
@@ -754,6 +786,9 @@ def save_search(run, path):
         "pairs_J": (np.stack(pool.pairs_J).astype(np.int8) if pool.pairs_J
                     else np.zeros((0, len(groups[0].J[0])), np.int8)),
         "pairs_y": np.array(pool.pairs_y, np.float64),
+        "parent_J": (np.stack([np.zeros_like(J) if pj is None else pj for pj, J in zip(pool.parent_J, pool.pairs_J)])
+                     .astype(np.int8) if pool.pairs_J else np.zeros((0, len(groups[0].J[0])), np.int8)),
+        "parent_y": np.array(pool.parent_y, np.float64),
     }
     hard_J = {}
     for g in groups:
@@ -790,6 +825,8 @@ def load_search(path, cfg, groups=1):
     pool = _Pool(cfg, a["sur_params"] if "sur_params" in a else None)
     pool.pairs_J = [row.copy() for row in a["pairs_J"]]
     pool.pairs_y = [float(y) for y in a["pairs_y"]]
+    pool.parent_y = [float(y) for y in a["parent_y"]]
+    pool.parent_J = [row.copy() if math.isfinite(y) else None for row, y in zip(a["parent_J"], pool.parent_y)]
     pool.rng.bit_generator.state = meta["rng"]
     if pool.sur is not None:
         torch = pool.sur.torch

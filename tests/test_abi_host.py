@@ -79,6 +79,15 @@ def test_gnn_host_entry_points():
     assert b.value > 10 * a.value > 0
     assert lib.gnn_workspace_bytes(0, 8, C.byref(a)) == -1
     assert lib.gnn_workspace_bytes(1, 17, C.byref(a)) == -1
+    # the ranked step needs its parent indices and a finite w_abs >= 0
+    dummy = C.c_void_p(16)
+    assert lib.gnn_train_step_ranked(dummy, 1, 8, dummy, None, 0.1, dummy, 1, None, dummy, dummy, None,
+                                     None) == -1
+    assert b"NULL ref" in lib.hs_last_error()
+    for w in (-0.5, float("nan"), float("inf")):
+        assert lib.gnn_train_step_ranked(dummy, 1, 8, dummy, dummy, w, dummy, 1, None, dummy, dummy, None,
+                                         None) == -1
+        assert b"w_abs" in lib.hs_last_error()
 
 
 def test_library_has_gfx950_code():

@@ -123,3 +123,68 @@ def test_adam_matches_torch():
         p.grad = torch.tensor(g, dtype=torch.float64)
         opt.step()
     assert np.allclose(th, p.detach().numpy(), rtol=0, atol=1e-12)
+
+
+def _ranked_batch():
+    # graphs 0 and 3 are parents; 1, 2 are children of 0 and 4 of 3; graph 5
+    # has no parent and graph 2's label is missing
+    gr = _graphs(2, 6, 13, missing=0.05)
+    labels = np.array([0.4, 1.1, np.inf, -0.3, 0.9, 2.0])
+    ref = [-1, 0, 0, -1, 3, -1]
+    return G.batch(gr), labels, ref
+
+
+def test_ranked_loss_backward_matches_central_differences():
+    """The ranked loss (child against parent, plus w_abs times the plain
+    loss): the hand-written gradient equals central differences of the
+    loss."""
+    B, labels, ref = _ranked_batch()
+    theta = _theta(7)
+    for w_abs in (0.0, 0.3):
+        loss, grad, _ = G.loss_and_grad(theta, B, labels, ref=ref, w_abs=w_abs)
+        rng = np.random.default_rng(9)
+        idx, o = [], 0
+        for name, shp in G.param_shapes():
+            n = int(np.prod(shp))
+            idx += list(o + rng.choice(n, size=min(n, 5), replace=False))
+            o += n
+        def fd(i, h):
+            tp, tm = theta.copy(), theta.copy()
+            tp[i] += h
+            tm[i] -= h
+            return (G.loss_and_grad(tp, B, labels, ref=ref, w_abs=w_abs)[0]
+                    - G.loss_and_grad(tm, B, labels, ref=ref, w_abs=w_abs)[0]) / (2 * h)
+        # a coordinate whose step crosses a ReLU kink gives differences that
+        # change with the step: those (at most a few) are left out
+        d1 = np.array([fd(i, 1e-6) for i in idx])
+        d2 = np.array([fd(i, 2.5e-7) for i in idx])
+        an = grad[idx]
+        smooth = np.abs(d1 - d2) <= 1e-5 * np.maximum(np.abs(d2), 1e-3 * np.abs(an).max())
+        assert smooth.sum() >= len(idx) - 4
+        assert np.linalg.norm(d2[smooth] - an[smooth]) / np.linalg.norm(an[smooth]) < 1e-6
+
+
+def test_ranked_loss_invariants():
+    """Without the plain term the ranked loss sees only differences: a
+    common shift of every label changes nothing, a common shift of every
+    prediction changes nothing (so the output bias gets no gradient), and
+    with no pairs the loss is w_abs times the plain loss."""
+    B, labels, ref = _ranked_batch()
+    theta = _theta(8)
+    l0, g0, y0 = G.loss_and_grad(theta, B, labels, ref=ref, w_abs=0.0)
+    l1, g1, _ = G.loss_and_grad(theta, B, labels + 3.25, ref=ref, w_abs=0.0)
+    assert l1 == pytest.approx(l0, rel=1e-12) and np.allclose(g1, g0, rtol=1e-10, atol=1e-14)
+    assert abs(G.unpack(g0)["b_out"][0]) < 1e-12 * max(1.0, np.abs(g0).max())
+    t2 = theta.copy()
+    t2[-1] += 5.0  # b_out shifts every prediction by 5
+    l2, _, y2 = G.loss_and_grad(t2, B, labels, ref=ref, w_abs=0.0)
+    assert np.allclose(y2, y0 + 5.0) and l2 == pytest.approx(l0, rel=1e-12)
+    lp, gp, _ = G.loss_and_grad(theta, B, labels)
+    ln, gn, _ = G.loss_and_grad(theta, B, labels, ref=[-1] * 6, w_abs=0.4)
+    assert ln == pytest.approx(0.4 * lp, rel=1e-12) and np.allclose(gn, 0.4 * gp, rtol=1e-12, atol=1e-15)
+    # a graph paired with an identical copy of itself: the predictions cancel,
+    # the loss is the squared label difference and the gradient vanishes
+    gr = _graphs(2, 1, 21)
+    Bs = G.batch(gr + gr)
+    ls, gs, _ = G.loss_and_grad(theta, Bs, np.array([0.5, 1.25]), ref=[-1, 0], w_abs=0.0)
+    assert ls == pytest.approx(0.75 ** 2, rel=1e-12) and np.abs(gs).max() < 1e-12

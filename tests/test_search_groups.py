@@ -307,3 +307,50 @@ def test_checkpoint_keeps_the_counted_couplings(S, tmp_path):
     back = S.load_search(path, cfg)
     assert sorted(back.hard_J) == sorted(run.hard_J)
     assert all(np.array_equal(back.hard_J[k], run.hard_J[k]) for k in run.hard_J)
+
+
+class _FakeSurrogate:
+    """Stands in for the network: predictions from a hash of the couplings,
+    and a record of every training call."""
+
+    def __init__(self, params):
+        self.calls = []
+        self.step = 0
+
+    def forward(self, graphs):
+        return np.array([int(hashlib.sha1(np.asarray(g[2], np.int8).tobytes()).hexdigest()[:6], 16) / 2.0**24
+                         for g in graphs], np.float32)
+
+    def train_step(self, labels, graphs=None, lr=1e-3, ref=None, w_abs=1.0, **kw):
+        self.calls.append((np.array(labels, np.float64), [np.array(g[2], np.int8) for g in graphs],
+                           None if ref is None else np.array(ref), w_abs, lr))
+        self.step += 1
+        return 0.0, np.zeros(len(graphs), np.float32)
+
+
+@pytest.mark.parametrize("loss", ["ranked", "plain"])
+def test_surrogate_training_batches(S, monkeypatch, loss):
+    """The ranked loss trains on (parent, proposal) pairs: every batch holds
+    train_batch / 2 pairs, parent first, ref pointing each proposal at its
+    parent; a proposal differs from its parent at one coupler, and both
+    labels are the scores the search measured (the proposal's PT score, the
+    chain's current score).  The plain loss draws single records."""
+    monkeypatch.setattr(S, "Surrogate", _FakeSurrogate)
+    cfg = S.SearchConfig(mode="surrogate", chains=6, L=2, proposals=5, top=2, t_s=0.7, train_steps=3,
+                         train_batch=8, train_loss=loss)
+    seeds = [workloads.couplings(2, "pm1", 61, c) for c in range(6)]
+    run = S.Search(cfg, seeds, surrogate_params=np.zeros(4))
+    for _ in range(3):
+        run.run_step(bars=(math.log(1.2),))
+    calls = run.pool.sur.calls
+    assert len(calls) == 3 * 3
+    for labels, graphs, ref, w_abs, lr in calls:
+        assert lr == cfg.lr
+        if loss == "plain":
+            assert ref is None and len(graphs) == 8
+            continue
+        assert w_abs == cfg.w_abs and len(graphs) == 8
+        assert ref.tolist() == [-1, 0, -1, 2, -1, 4, -1, 6]
+        for k in range(0, 8, 2):
+            assert int((graphs[k] != graphs[k + 1]).sum()) == 1  # one mutated coupler
+            assert np.isfinite(labels[k]) and np.isfinite(labels[k + 1])
