@@ -100,6 +100,9 @@ def parse():
     p.add_argument("--validate", choices=["during", "after"], default="during",
                    help="search workloads: re-score counted states on a stream of their own while the search "
                         "runs (during), or after its last step")
+    p.add_argument("--gnn-cus", type=int, default=0,
+                   help="surrogate arm: compute units set aside for the surrogate's kernels (0: none); the arm's PT "
+                        "launches use the others")
     p.add_argument("--hw-queues", type=int, default=8,
                    help="search workloads: hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32); "
                         "the chain groups and the validation stream each need one")
@@ -482,6 +485,7 @@ def search(args):
     bars = {"ln3": math.log(3.0), "ln10": math.log(10.0), "ln30": math.log(30.0)}
     arms = {}
     for mode in ("plain", "surrogate", "random"):
+        S.set_gnn_cus(args.gnn_cus if mode == "surrogate" else 0)
         cfg = S.SearchConfig(mode=mode, chains=args.search_chains, top=args.search_top)
         params = workloads.gnn_params(hs.lib().gnn_param_count(), hs.gnn_fan_ins())
         t0 = time.perf_counter()
@@ -528,7 +532,8 @@ def search(args):
                                "mutations in +-1..+-7, 32 restarts K32 R2, T_s 0.5",
                    "bounded_steps": args.search_steps, "chain_groups": args.search_groups,
                    "screen": f"16 proposals, top {args.search_top} scored by PT",
-                   "validation": args.validate, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
+                   "validation": args.validate, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
+                   "surrogate_cus": args.gnn_cus},
         "chip_share_note": "chip shares are spin-flip attempts x 22 ops over the wall, as a fraction of the "
                            "ALU peak; the sweep kernel's own full-batch fraction (C8 benchmark) bounds them",
         "surrogate_over_plain": (rate("surrogate") / rate("plain")) if rate("plain") > 0 else None,

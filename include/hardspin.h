@@ -217,6 +217,22 @@ int pt_destroy(hs_pt *h);
 int pt_launch_shape(const hs_pt *h, int32_t *grid, int32_t *block_waves, int32_t *lds_bytes, int32_t *work_items,
                     int64_t *lane_sites);
 
+/* A stream (default priority) whose kernels run only on compute units
+ * cu_first .. cu_first + cu_count - 1 of the current device
+ * (hipExtStreamCreateWithCUMask).  A persistent sweep launch holds every CU
+ * it reaches until its work queue is empty, so small kernels that must not
+ * wait for it (the surrogate's screen and training inside the instance
+ * search, Algorithm 1) get CUs of their own this way, and the sweep
+ * launches a stream over the rest.  Kernels launched on such a stream keep
+ * their grids; workgroups beyond the CUs' capacity start as others finish.
+ * *stream receives the handle; HS_EINVAL for a NULL stream or a range
+ * outside the device, HS_EHIP if the runtime refuses.  Host only. */
+int hs_stream_create_cus(int32_t cu_first, int32_t cu_count, void **stream);
+
+/* Destroys a stream made by hs_stream_create_cus (after its work has
+ * finished, as hipStreamDestroy).  NULL is a no-op. */
+int hs_stream_destroy(void *stream);
+
 /* One RAO move (Algorithm 1, Sec. II.A) as a pure host function.
  * (w0, w1, w2, w3) = Philox((chain, seed), (step, proposal, 0, 4)); the
  * coupler is the e-th live one in canonical order, e = floor(w0 E_live /

@@ -134,6 +134,8 @@ def lib():
         L.gnn_train_step.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                      C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(hs_adam), C.c_void_p]
+        L.hs_stream_create_cus.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]
+        L.hs_stream_destroy.argtypes = [C.c_void_p]
         L.gnn_train_step_ranked.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_float,
                                             C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p, C.c_void_p,
                                             C.POINTER(hs_adam), C.c_void_p]
@@ -168,7 +170,7 @@ def exported_symbols():
             "hardness_eval", "gnn_param_count", "gnn_workspace_bytes", "gnn_prepare", "gnn_forward",
             "gnn_train_step", "pt_sweep_record", "walk_autocorr", "walk_tau", "lao_cycle_count", "lao_init",
             "lao_move", "pt_capture", "overlap_analyze", "pt_launch_shape", "hardness_eval_static",
-            "gnn_train_step_ranked"]
+            "gnn_train_step_ranked", "hs_stream_create_cus", "hs_stream_destroy"]
 
 
 def _check(rc):
@@ -207,6 +209,16 @@ class _HostInstances:
 def _torch():
     import torch
     return torch
+
+
+def cu_stream(cu_first, cu_count):
+    """A torch stream (wrapping hs_stream_create_cus) whose kernels run only
+    on CUs cu_first .. cu_first + cu_count - 1.  The stream lives as long as
+    the process (torch's caching allocator keeps blocks per stream)."""
+    torch = _torch()
+    h = C.c_void_p()
+    _check(lib().hs_stream_create_cus(int(cu_first), int(cu_count), C.byref(h)))
+    return torch.cuda.ExternalStream(h.value)
 
 
 def _stream_ptr(stream):
@@ -419,7 +431,9 @@ def hardness_eval(cands, n_restarts, K, R, beta, swap_interval, s_max, seed, blo
                            block_waves, rs.ctypes.data)
     nb = C.c_size_t(0)
     _check(lib().hardness_workspace_bytes(hi.arr, len(cands), C.byref(p), C.byref(nb)))
-    scratch = torch.zeros(max(16, nb.value), dtype=torch.uint8, device="cuda")
+    # hardness_eval writes every scratch byte its launch reads: no fill kernel
+    # (which would wait for CUs held by other streams' persistent launches)
+    scratch = torch.empty(max(16, nb.value), dtype=torch.uint8, device="cuda")
     ln = np.zeros(len(cands), np.float64)
     det = (hs_tts_detail * max(1, len(cands)))()
     _check(lib().hardness_eval(hi.arr, len(cands), C.byref(p), C.c_void_p(scratch.data_ptr()),

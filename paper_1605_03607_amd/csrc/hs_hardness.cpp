@@ -230,6 +230,31 @@ int hardness_eval(const hs_instance *cands, int n, const hs_hardness_params *p, 
     return run_hardness(n, p, runs, d, L, reinterpret_cast<char *>(scratch_buf), ln_tts_out, detail, stream);
 }
 
+int hs_stream_create_cus(int32_t cu_first, int32_t cu_count, void **stream)
+{
+    if (stream == nullptr) return fail(HS_EINVAL, "hs_stream_create_cus: NULL stream");
+    int dev = 0, n = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return fail(HS_EHIP, std::string("hs_stream_create_cus: ") + hipGetErrorString(e));
+    if (cu_first < 0 || cu_count < 1 || int64_t(cu_first) + cu_count > n)
+        return fail(HS_EINVAL, "hs_stream_create_cus: CU range outside the device's " + std::to_string(n));
+    std::vector<uint32_t> mask((n + 31) / 32, 0u);
+    for (int c = cu_first; c < cu_first + cu_count; ++c) mask[c / 32] |= 1u << (c % 32);
+    hipStream_t st = nullptr;
+    e = hipExtStreamCreateWithCUMask(&st, uint32_t(mask.size()), mask.data());
+    if (e != hipSuccess) return fail(HS_EHIP, std::string("hs_stream_create_cus: ") + hipGetErrorString(e));
+    *stream = st;
+    return HS_OK;
+}
+
+int hs_stream_destroy(void *stream)
+{
+    if (stream == nullptr) return HS_OK;
+    const hipError_t e = hipStreamDestroy(reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HS_OK : fail(HS_EHIP, std::string("hs_stream_destroy: ") + hipGetErrorString(e));
+}
+
 int hardness_eval_static(const hs_instance *cands, int n, const hs_hardness_params *p, double *ln_tts_out,
                          hs_tts_detail *detail, void *stream)
 {

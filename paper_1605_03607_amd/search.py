@@ -203,7 +203,7 @@ class Search:
         flat = [J for pr in props for (J, _, _) in pr]
         pool = self.pool
         pred = []
-        with pool.lock:  # every call ends with a host copy: nothing is left in flight
+        with pool.lock, _gnn_context():  # every call ends with a host copy: nothing is left in flight
             t0 = time.perf_counter()
             for a in range(0, len(flat), c.screen_chunk):
                 pred.append(pool.sur.forward([(c.L, None, J) for J in flat[a:a + c.screen_chunk]]))
@@ -215,7 +215,7 @@ class Search:
         pool = self.pool
         if pool.sur is None:
             return
-        with pool.lock:
+        with pool.lock, _gnn_context():
             t0 = time.perf_counter()
             if c.train_loss == "ranked":
                 # batches of train_batch / 2 (parent, proposal) pairs: the
@@ -293,7 +293,36 @@ class Search:
         self.step += 1
 
 
-_STREAMS = []
+_STREAMS = {}
+_STREAMS_LOCK = threading.Lock()
+_GNN_CUS = 0  # compute units set aside for the surrogate's kernels (0: none)
+
+
+def set_gnn_cus(n):
+    """Sets aside the device's last n compute units for the surrogate: the
+    streams made afterwards for chain groups and validation run their PT
+    launches on the other CUs, and the surrogate's screen and training run
+    on these n (0: every stream uses every CU).  A persistent PT launch
+    holds each CU it reaches until its queue is empty, so without this the
+    surrogate's small kernels wait for the other groups' launches to drain."""
+    global _GNN_CUS
+    _GNN_CUS = int(n)
+
+
+def _stream(kind, i):
+    import torch
+    from . import cu_stream
+    key = (kind, i, _GNN_CUS)
+    with _STREAMS_LOCK:
+        if key not in _STREAMS:
+            if _GNN_CUS:
+                n = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+                if not 0 < _GNN_CUS < n:
+                    raise ValueError(f"cannot set aside {_GNN_CUS} of {n} CUs")
+                _STREAMS[key] = cu_stream(n - _GNN_CUS, _GNN_CUS) if kind == "gnn" else cu_stream(0, n - _GNN_CUS)
+            else:
+                _STREAMS[key] = torch.cuda.Stream()
+        return _STREAMS[key]
 
 
 def _group_stream(i):
@@ -303,9 +332,18 @@ def _group_stream(i):
     memory of an earlier one instead of allocating afresh while other
     groups' kernels run."""
     import torch
-    while len(_STREAMS) <= i:
-        _STREAMS.append(torch.cuda.Stream())
-    return _STREAMS[i], torch.cuda.stream(_STREAMS[i])
+    s = _stream("pt", i)
+    return s, torch.cuda.stream(s)
+
+
+def _gnn_context():
+    """Context for the surrogate's calls: its own stream on the CUs set aside
+    by set_gnn_cus, else the caller's current stream."""
+    import contextlib
+    if not _GNN_CUS:
+        return contextlib.nullcontext()
+    import torch
+    return torch.cuda.stream(_stream("gnn", 0))
 
 
 def _in_groups(n, fn):

@@ -90,6 +90,16 @@ def test_gnn_host_entry_points():
         assert b"w_abs" in lib.hs_last_error()
 
 
+def test_cu_stream_entry_points_check_their_arguments():
+    """hs_stream_create_cus needs somewhere to put the stream; destroying
+    NULL is a no-op (no GPU needed for either)."""
+    hs = _hs()
+    lib = hs.lib()
+    assert lib.hs_stream_create_cus(0, 8, None) == -1
+    assert b"NULL stream" in lib.hs_last_error()
+    assert lib.hs_stream_destroy(None) == 0
+
+
 def test_library_has_gfx950_code():
     hs = _hs()
     # the embedded offload bundle names its target

@@ -197,3 +197,32 @@ def test_validation_during_the_search(direction):
     o = oracle.hardness_eval(L, None, run.hard_J[k], S.validation_id(k), S.validation_seed(cfg), 8, cfg.K, cfg.R,
                              cfg.beta, cfg.swap_interval, cfg.s_max)
     assert got["fresh"][k] == (o["ln_tts"], o["confirmed"])
+
+
+def test_compute_units_set_aside_for_the_surrogate():
+    """With CUs set aside for the surrogate (its kernels on a CU-masked
+    stream, the groups' PT launches on the rest), a random-screened search
+    takes exactly the decisions of one without the split, and a surrogate
+    search runs its screen and training on the set-aside stream."""
+    hs = _gpu()
+    from paper_1605_03607_amd import search as S
+    chains = 6
+    cfg = S.SearchConfig(mode="random", chains=chains, L=3, restarts=4, K=8, R=2, s_max=4000, proposals=5, top=2)
+    seeds = [workloads.couplings(3, "pm1", 97, c) for c in range(chains)]
+    try:
+        S.set_gnn_cus(0)
+        plain = S.GroupedSearch(cfg, seeds, groups=2)
+        plain.run(3, bars=(math.log(1.5),))
+        S.set_gnn_cus(16)
+        split = S.GroupedSearch(cfg, seeds, groups=2)
+        split.run(3, bars=(math.log(1.5),))
+        assert split.decisions == plain.decisions and np.array_equal(split.ln, plain.ln)
+        scfg = S.SearchConfig(mode="surrogate", chains=chains, L=3, restarts=4, K=8, R=2, s_max=4000, proposals=5,
+                              top=2, train_steps=2, train_batch=4)
+        params = workloads.gnn_params(hs.lib().gnn_param_count(), hs.gnn_fan_ins())
+        sur = S.GroupedSearch(scfg, seeds, groups=2, surrogate_params=params)
+        sur.run(3, bars=(math.log(1.5),))
+        assert len(sur.decisions) == 3 * chains and sur.pool.sur.step > 0
+        assert np.isfinite(sur.pool.sur.params.cpu().numpy()).all()
+    finally:
+        S.set_gnn_cus(0)
