@@ -150,8 +150,9 @@ def cpu_baseline(cfg, insts, budget_s):
                       f"{el:.1f} s wall"}
 
 
-# Host threads the CPU baselines use at most: a one-GPU machine's CPU share is 16
-# threads, whatever count the operating system reports for the whole machine.
+# Host threads the CPU baselines use at most: 16, a per-GPU share of a
+# many-core host, whatever count the operating system reports for the whole
+# machine (the count actually used is recorded with every baseline).
 HOST_THREAD_CAP = 16
 
 
@@ -174,7 +175,7 @@ def host_info():
     aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
     return {"host_cpu_model": model, "host_nproc": os.cpu_count(), "host_affinity_cpus": aff,
             "thread_cap": HOST_THREAD_CAP,
-            "thread_cap_reason": "a one-GPU box's CPU share is 16 threads; cores = min(affinity CPUs, cap, "
+            "thread_cap_reason": "at most 16 threads, a per-GPU share of the host; cores = min(affinity CPUs, cap, "
                                  "instances in the sample)"}
 
 
@@ -187,7 +188,7 @@ def emit(line):
 
 
 def measured_issue_rates():
-    """Issue rates of single instruction classes measured on the box
+    """Issue rates of single instruction classes measured on an MI355X
     (bench.py --probe), from the committed summary, or None."""
     try:
         with open(ISSUE_RATES_FILE) as f:
