@@ -74,6 +74,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--block-waves", type=int, default=0)
+    p.add_argument("--lattice", type=int, default=8,
+                   help="batch workload: Chimera side L of the 256 instances (8: the C8 benchmark; other sizes show "
+                        "how the per-sweep costs amortise)")
     p.add_argument("--swap-interval", type=int, default=None,
                    help="sweeps between exchange passes (default: the workload's)")
     p.add_argument("--copy-mib", type=int, default=0,
@@ -941,6 +944,11 @@ def main():
 
     import paper_1605_03607_amd as hs
     cfg = workloads.batch_c8()
+    if args.lattice != 8:
+        if not 1 <= args.lattice <= 16:
+            print(json.dumps({"error": "--lattice must be in 1..16"}))
+            sys.exit(2)
+        cfg.update(L=args.lattice, name=f"C{args.lattice} x256, K32 R2, +-7")
     if args.swap_interval is not None:
         cfg["swap_interval"] = args.swap_interval
     sweeps = args.sweeps or cfg["sweeps"]
@@ -979,11 +987,12 @@ def main():
     value = attempts_per_step * args.steps / wall
     k_avg_s = float(np.mean(kernel_ms)) / 1e3
     roof = alu_roofline(attempts_per_step, k_avg_s)
-    roof.update({"traffic": measured_traffic(), "kernel_ms_avg": float(np.mean(kernel_ms)),
+    roof.update({"traffic": measured_traffic() if cfg["L"] == 8 else None,
+                 "kernel_ms_avg": float(np.mean(kernel_ms)),
                  "kernel": "hs::dev::k_pt_sweep", "kernel_fingerprint": kernel_fingerprint(),
                  "issue_rates_measured_lane_ops_per_s": measured_issue_rates()})
     out = {
-        "metric": "spin-flip attempts/s (C8 PT batch)",
+        "metric": f"spin-flip attempts/s (C{cfg['L']} PT batch)",
         "value": value,
         "unit": "spin-flip attempts/s",
         "n_gpus": 1,
@@ -996,7 +1005,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "instances": n_inst, "L": cfg["L"], "N": n_sites,
-                   "couplers": 1472, "K": cfg["K"], "R": cfg["R"], "sweeps_per_step": sweeps,
+                   "couplers": 24 * cfg["L"] ** 2 - 8 * cfg["L"], "K": cfg["K"], "R": cfg["R"],
+                   "sweeps_per_step": sweeps,
                    "swap_interval": cfg["swap_interval"], "alphabet": "+-1..+-7"},
         "roofline": roof,
         "energy_mismatches": mism,
