@@ -74,6 +74,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--block-waves", type=int, default=0)
+    p.add_argument("--instances", type=int, default=256,
+                   help="batch workload: number of instances (256: the benchmark)")
     p.add_argument("--lattice", type=int, default=8,
                    help="batch workload: Chimera side L of the 256 instances (8: the C8 benchmark; other sizes show "
                         "how the per-sweep costs amortise)")
@@ -949,6 +951,11 @@ def main():
             print(json.dumps({"error": "--lattice must be in 1..16"}))
             sys.exit(2)
         cfg.update(L=args.lattice, name=f"C{args.lattice} x256, K32 R2, +-7")
+    if args.instances != 256:
+        if args.instances < 1:
+            print(json.dumps({"error": "--instances must be positive"}))
+            sys.exit(2)
+        cfg.update(n_inst=args.instances, name=cfg["name"].replace("x256", f"x{args.instances}"))
     if args.swap_interval is not None:
         cfg["swap_interval"] = args.swap_interval
     sweeps = args.sweeps or cfg["sweeps"]
@@ -987,7 +994,7 @@ def main():
     value = attempts_per_step * args.steps / wall
     k_avg_s = float(np.mean(kernel_ms)) / 1e3
     roof = alu_roofline(attempts_per_step, k_avg_s)
-    roof.update({"traffic": measured_traffic() if cfg["L"] == 8 else None,
+    roof.update({"traffic": measured_traffic() if (cfg["L"], n_inst) == (8, 256) else None,
                  "kernel_ms_avg": float(np.mean(kernel_ms)),
                  "kernel": "hs::dev::k_pt_sweep", "kernel_fingerprint": kernel_fingerprint(),
                  "issue_rates_measured_lane_ops_per_s": measured_issue_rates()})
