@@ -105,6 +105,11 @@ def parse():
     p.add_argument("--validate", choices=["during", "after"], default="during",
                    help="search workloads: re-score counted states on a stream of their own while the search "
                         "runs (during), or after its last step")
+    p.add_argument("--search-block-waves", default="auto",
+                   help="search workload: wavefronts per PT workgroup of hardness_eval, 0 for the library's choice "
+                        "(16 at C8), or auto: 16 for the plain arm, whose steps wait for their slowest restart, and "
+                        "8 for the screened arms, which score twice the restarts per step and gain more from two "
+                        "workgroups per CU than they lose on the slowest restart (measured)")
     p.add_argument("--gnn-cus", type=int, default=0,
                    help="surrogate arm: compute units set aside for the surrogate's kernels (0: none); the arm's PT "
                         "launches use the others")
@@ -448,6 +453,12 @@ TTS_READING = ("ln TTS = ln(sweeps of all restarts / restarts whose minimum is t
                "workload description names")
 
 
+def _search_block_waves(args, mode):
+    if args.search_block_waves == "auto":
+        return 16 if mode == "plain" or args.search_top < 2 else 8
+    return int(args.search_block_waves)
+
+
 def _run_validated(args, S, run, seeds, bars, name):
     """The timed steps of a search and the validation of its counted states:
     during the search (a Validator on the stream after the groups' ones) or
@@ -492,7 +503,8 @@ def search(args):
     arms = {}
     for mode in ("plain", "surrogate", "random"):
         S.set_gnn_cus(args.gnn_cus if mode == "surrogate" else 0)
-        cfg = S.SearchConfig(mode=mode, chains=args.search_chains, top=args.search_top)
+        cfg = S.SearchConfig(mode=mode, chains=args.search_chains, top=args.search_top,
+                             block_waves=_search_block_waves(args, mode))
         params = workloads.gnn_params(hs.lib().gnn_param_count(), hs.gnn_fan_ins())
         t0 = time.perf_counter()
         run = S.GroupedSearch(cfg, seeds, groups=args.search_groups,
@@ -510,6 +522,7 @@ def search(args):
             "init_seconds": t_init, "pt_seconds": run.pt_seconds, "gnn_seconds": run.gnn_seconds,
             "pt_sweeps": int(run.pt_sweeps), "accepted": run.accepted, "h0_ln_tts": run.h0,
             "pt_device_ms": run.pt_device_ms, "pt_attempts": int(run.pt_attempts), "pt_calls": run.pt_calls,
+            "pt_block_waves": cfg.block_waves,
             "validated_hard_instances": {name: val["counts"][b] for name, b in bars.items()},
             "validated_hard_instances_per_hour": {name: val["counts"][b] / v_hours for name, b in bars.items()},
             "validation": _validation_record(
@@ -539,7 +552,7 @@ def search(args):
                    "bounded_steps": args.search_steps, "chain_groups": args.search_groups,
                    "screen": f"16 proposals, top {args.search_top} scored by PT",
                    "validation": args.validate, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
-                   "surrogate_cus": args.gnn_cus},
+                   "surrogate_cus": args.gnn_cus, "pt_block_waves": args.search_block_waves},
         "chip_share_note": "chip shares are spin-flip attempts x 22 ops over the wall, as a fraction of the "
                            "ALU peak; the sweep kernel's own full-batch fraction (C8 benchmark) bounds them",
         "surrogate_over_plain": (rate("surrogate") / rate("plain")) if rate("plain") > 0 else None,

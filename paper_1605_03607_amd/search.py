@@ -50,6 +50,13 @@ ALPHABET_PM7 = np.array([-7, -6, -5, -4, -3, -2, -1, 1, 2, 3, 4, 5, 6, 7], np.in
 ALPHABET_PM1 = np.array([-1, 1], np.int8)  # Algorithm 1's sign flips
 
 
+def _launch(c):
+    """hardness_eval's launch shape for config c: the wavefronts per
+    workgroup when set (results do not depend on it), else the library's
+    choice."""
+    return {"block_waves": c.block_waves} if c.block_waves else {}
+
+
 def _timed_hardness(cands, c):
     """hardness_eval on the calling thread's current stream, with the device
     span of the call from events recorded on that stream: (ln, details, ms,
@@ -57,7 +64,7 @@ def _timed_hardness(cands, c):
     import torch
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
-    ln, det = hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed)
+    ln, det = hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed, **_launch(c))
     end.record()
     end.synchronize()
     lanes_sites = c.K * c.R * 8 * c.L * c.L
@@ -74,7 +81,7 @@ class SearchConfig:
     def __init__(self, mode="plain", chains=64, L=8, restarts=32, K=32, R=2, beta=(0.1, 5.0),
                  swap_interval=1, s_max=100_000, t_s=0.5, seed=1605, proposals=16, top=2,
                  train_steps=32, train_batch=32, lr=3e-3, replay=4096, screen_chunk=128, direction=1,
-                 alphabet=ALPHABET_PM7, train_loss="ranked", w_abs=0.1):
+                 alphabet=ALPHABET_PM7, train_loss="ranked", w_abs=0.1, block_waves=0):
         if direction not in (1, -1):
             raise ValueError("direction is +1 (harder) or -1 (easier)")
         self.mode = mode
@@ -90,6 +97,9 @@ class SearchConfig:
         if train_loss not in ("ranked", "plain"):
             raise ValueError("train_loss is 'ranked' or 'plain'")
         self.train_loss, self.w_abs = train_loss, float(w_abs)
+        # wavefronts per PT workgroup (0: the library's choice); a launch
+        # shape, so it changes no result and is not part of a checkpoint
+        self.block_waves = int(block_waves)
 
 
 def _key(J):
@@ -516,7 +526,7 @@ def _fresh_scores(cands, c, restarts, seed_v):
     import torch
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
-    y, det = hardness_eval(cands, restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, seed_v)
+    y, det = hardness_eval(cands, restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, seed_v, **_launch(c))
     end.record()
     end.synchronize()
     sweeps = sum(int(dd["sweeps_total"]) for dd in det)

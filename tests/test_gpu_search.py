@@ -226,3 +226,20 @@ def test_compute_units_set_aside_for_the_surrogate():
         assert np.isfinite(sur.pool.sur.params.cpu().numpy()).all()
     finally:
         S.set_gnn_cus(0)
+
+
+def test_hardness_does_not_depend_on_the_launch_shape():
+    """hardness_eval with 4-, 8- and 16-wavefront workgroups (the search's
+    screened arms run with 8): identical ln TTS, ground-state energies,
+    confirmations and per-restart sweep counts."""
+    hs = _gpu()
+    from paper_1605_03607_amd import search as S
+    c = S.SearchConfig(L=3, restarts=6, K=8, R=2, s_max=4000)
+    cands = [dict(L=3, J=workloads.couplings(3, "pm7", 101, i), live=None, instance_id=i) for i in range(6)]
+    out = []
+    for bw in (16, 8, 4):
+        ln, det = hs.hardness_eval(cands, c.restarts, c.K, c.R, c.beta, c.swap_interval, c.s_max, c.seed,
+                                   block_waves=bw)
+        out.append((np.asarray(ln), [(d["e_gs"], d["confirmed"], d["restart_sweeps"].tolist()) for d in det]))
+    for ln, det in out[1:]:
+        assert np.array_equal(ln, out[0][0]) and det == out[0][1]
