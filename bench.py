@@ -558,6 +558,10 @@ def search(args):
         "surrogate_over_plain": (rate("surrogate") / rate("plain")) if rate("plain") > 0 else None,
         "surrogate_over_plain_unvalidated": (raw("surrogate") / raw("plain")) if raw("plain") > 0 else None,
         "random_over_plain": (rate("random") / rate("plain")) if rate("plain") > 0 else None,
+        "surrogate_over_plain_by_bar": {
+            b: (arms["surrogate"]["validated_hard_instances_per_hour"][b] /
+                arms["plain"]["validated_hard_instances_per_hour"][b])
+            if arms["plain"]["validated_hard_instances_per_hour"][b] > 0 else None for b in bars},
         "arms": arms,
         "roofline": pt_roofline(sum(a["pt_attempts"] for a in arms.values()),
                                 sum(a["pt_device_ms"] for a in arms.values()),
