@@ -314,7 +314,9 @@ def set_gnn_cus(n):
     launches on the other CUs, and the surrogate's screen and training run
     on these n (0: every stream uses every CU).  A persistent PT launch
     holds each CU it reaches until its queue is empty, so without this the
-    surrogate's small kernels wait for the other groups' launches to drain."""
+    surrogate's small kernels wait for the other groups' launches to drain.
+    Measured on the C8 search, the PT launches lose more on the remaining
+    CUs than the surrogate gains, so the default is 0."""
     global _GNN_CUS
     _GNN_CUS = int(n)
 
