@@ -224,11 +224,13 @@ void build_tables(int K, const double *beta, int64_t d_cap, HostTables &t)
     t.ts_dhi.assign(K, 0);
     t.ts_dmax.assign(K, 0);
     t.ts_full_row.assign(K, 0);
+    t.ts_rate.assign(K, 0.0f);
     t.ts_hi.clear();
     t.ts_full.clear();
     for (int k = 0; k + 1 < K; ++k) {
         t.ts_row[k] = int32_t(t.ts_hi.size());
         t.ts_full_row[k] = int32_t(t.ts_full.size());
+        t.ts_rate[k] = float(std::log(2.0) / (beta[k + 1] - beta[k]));
         int64_t d = 1;
         for (; d <= d_cap; ++d) {
             const uint64_t T = swap_threshold(beta[k], beta[k + 1], d);

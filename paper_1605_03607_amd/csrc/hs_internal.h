@@ -69,6 +69,7 @@ struct alignas(16) TableDev {
     int64_t ts_hi_off;             // uint16 as uint32 pairs: fast exchange thresholds (high 16 bits)
     int64_t ts_full_off;           // uint32: exact exchange thresholds
     int64_t ts_full_row_off;       // int32 [K]: start of row k in the exact table
+    int64_t ts_rate_off;           // float [K]: ln 2 / (beta_{k+1} - beta_k) of pair (k, k+1)
 };
 
 // Fast Metropolis threshold: thi = T >> 16 for m >= 1, 0x10000 for m <= 0
@@ -83,6 +84,7 @@ struct HostTables {
     std::vector<int32_t> ts_row, ts_dhi, ts_dmax, ts_full_row;
     std::vector<uint16_t> ts_hi;            // concatenated rows
     std::vector<uint32_t> ts_full;          // concatenated rows
+    std::vector<float> ts_rate;             // [K]: ln 2 / (beta_{k+1} - beta_k)
 };
 
 struct HostInstance {

@@ -22,10 +22,12 @@
 //     signed 16-bit arithmetic compares it with the uniforms; with 4-byte
 //     columns the per-lane gather is free of bank conflicts.  The exact table
 //     T = floor(2^32 exp(-2 beta m)) stays in global memory for ties.
-//   * Exchange passes: every wavefront evaluates part of the acceptance tests
-//     of pair (k, k+1) for every configuration that can be carried into slot
-//     k, then one wavefront per replica set links the runs of accepted
-//     exchanges and rewrites perm.
+//   * Exchange passes: one wavefront per replica set turns each pair's
+//     uniform into the largest energy difference the pair accepts, walks the
+//     runs of accepted exchanges and rewrites perm.  (Packed launches, and
+//     pt_swap, evaluate the acceptance tests of pair (k, k+1) for every
+//     configuration that can be carried into slot k across the wavefronts
+//     first, then link the runs.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -225,6 +227,9 @@ struct LdsLayout {
     // packed launches only: replica-set segments, exchange-test decodes,
     // the members' coupling words and flip masks, threshold-row offsets
     uint32_t seg, dec, jwl, lml, thia;
+    // unpacked launches: the first two Metropolis draws of the next sweep for
+    // the (at most two) wavefronts that walk the exchange runs
+    uint32_t hand;
 };
 
 // mode bit 0: 2-byte threshold columns (else 4-byte: no two lanes share a
@@ -232,6 +237,9 @@ struct LdsLayout {
 // counts the replica sets of all members, ntest_max their exchange tests, and
 // the exchange tables stay in global memory).
 constexpr int kLdsPacked = 2;
+// mode bit 2 (unpacked launches): room for the exchange walkers' hand-over
+// of their first two draws of the next sweep
+constexpr int kLdsHand = 4;
 
 __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int r_max, int mode,
                                                 int ntest_max = 0)
@@ -253,14 +261,20 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int
     l.ux = o;
     o += 64 * 4;                                  // uniforms of the exchange pass, pair r (K-1) + k
     l.xrow = o;
-    // exchange-table row start and length of pair (k, k+1); packed launches
-    // also the exact table's row start and length, by the pair's lower slot
-    o += ((mode & kLdsPacked) ? 4 : 2) * 64 * 4;
+    // exchange-table row start and length of pair (k, k+1), the exact
+    // table's row start and length (packed launches: by the pair's lower
+    // slot), and beta_{k+1} - beta_k
+    o += 5 * 64 * 4;
     l.stopv = o;
     o += uint32_t(r_max) * 64 * 4;                // run ends of the exchange pass, [set][start]
     l.misc = o;
     o += 16 * 4;
-    l.seg = l.dec = l.jwl = l.lml = l.thia = o;
+    l.seg = l.dec = l.jwl = l.lml = l.thia = l.hand = o;
+    if ((mode & kLdsHand) && !(mode & kLdsPacked)) {
+        o = (o + 15u) & ~15u;
+        l.hand = o;
+        o += 4 * 64 * 16;                         // uint4 [walker][draw][lane]
+    }
     if (mode & kLdsPacked) {
         l.seg = o;
         o += 2 * 64 * 4;                          // first slot and K of every replica set
@@ -439,6 +453,108 @@ __device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm
             const int np = j == e ? ox : on;
             perm[base + j] = np;
             if (j < K - 1 && j != e) atomicAdd(&sacc[j * R + r], 1u);
+        }
+    }
+}
+
+// The exchange pass by critical energy differences (unpacked launches).  For
+// pair (k, k+1) with uniform u the test "d <= 0 or u < T_k(d)" accepts a set
+// of differences closed downwards, since T_k(d) = floor(2^32 e^{-(beta_{k+1} -
+// beta_k) d}) does not grow with d (0 beyond the table): it accepts exactly
+// d <= D_k, D_k >= 0 the largest difference it accepts.  A configuration of
+// energy E carried into slot k therefore moves on iff E <= B_k = E_{k+1} + D_k,
+// and one wavefront per replica set finds the runs of the ascending pass by a
+// scalar walk: the run from x ends at the first pair k >= x with E_x > B_k.
+// D_k needs no energies, so the wavefront that draws the pass's uniforms
+// computes it before the phase barrier.  It starts from the real bound
+// (u < 2^32 e^{-db d} iff d < (32 - log2 u) ln 2 / db) and is settled on the
+// integer tables, so every decision equals the test's.
+//
+// xrow: [k] fast-table row start, [64 + k] its length dhi, [128 + k] exact
+// table row start, [192 + k] its length dmax, [256 + k] ln 2 / (beta_{k+1} -
+// beta_k) (float bits).
+__device__ __forceinline__ void load_xrows_walk(int32_t *xrow, const TableDev &tb, const uint32_t *ws32, int K,
+                                                int i)
+{
+    if (i < 64) {
+        const bool ok = i < K - 1;
+        xrow[i] = ok ? int32_t(ws32[tb.ts_row_off + i]) : 0;
+        xrow[64 + i] = ok ? int32_t(ws32[tb.ts_dhi_off + i]) : 0;
+        xrow[128 + i] = ok ? int32_t(ws32[tb.ts_full_row_off + i]) : 0;
+        xrow[192 + i] = ok ? int32_t(ws32[tb.ts_dmax_off + i]) : 0;
+        xrow[256 + i] = ok ? int32_t(ws32[tb.ts_rate_off + i]) : 0;
+    }
+}
+
+// D_k for pair k (0 <= k < K - 1) and uniform u: the largest difference the
+// pair accepts.
+template <bool kLds>
+__device__ __forceinline__ int pair_limit(uint32_t u, int k, const int32_t *xrow, const TableDev &tb,
+                                          const uint32_t *ws32, const uint16_t *tshi)
+{
+    const uint16_t *hi = kLds ? tshi : reinterpret_cast<const uint16_t *>(ws32 + tb.ts_hi_off);
+    const uint32_t *full = ws32 + tb.ts_full_off;
+    const int row = xrow[k], dh = xrow[64 + k], frow = xrow[128 + k], dmax = xrow[192 + k];
+    const float rate = __int_as_float(xrow[256 + k]);
+    // u < T(d) for 1 <= d <= dmax: the 16-bit table decides unless the high
+    // halves tie (h = the table's entry d, 0 beyond its length)
+    const uint32_t u16 = u >> 16;
+    auto acc = [&](int d, uint32_t h) -> bool { return u16 != h ? u16 < h : u < full[frow + d - 1]; };
+    auto hi_at = [&](int d) -> uint32_t {
+        return d <= dh ? uint32_t(hi[row + min(max(d, 1), max(dh, 1)) - 1]) : 0u;
+    };
+    // log2(0) = -inf gives +inf, clamped to the table
+    const float x = fminf(fmaxf((32.0f - __builtin_amdgcn_logf(float(u))) * rate, 0.0f), float(dmax) + 1.0f);
+    int D = min(max(int(ceilf(x)) - 1, 0), dmax);
+    // entries D + 1 and D, read together
+    const uint32_t h1 = hi_at(D + 1), h0 = hi_at(D);
+    const bool a1 = D < dmax && acc(D + 1, h1);
+    const bool a0 = D == 0 || acc(D, h0);
+    if (a1) {
+        ++D;
+        while (D < dmax && acc(D + 1, hi_at(D + 1))) ++D;
+    } else if (!a0) {
+        --D;
+        while (D > 0 && !acc(D, hi_at(D))) --D;
+    }
+    return D;
+}
+
+// The runs of one exchange pass and the new perm, from xd[r (K-1) + k] = D_k
+// of every pair (wavefront r mod nwaves for set r, lane j = slot).
+__device__ void exchange_walk(int K, int R, int wave, int nwaves, const int32_t *Es, const int32_t *xd,
+                              int32_t *perm, uint32_t *sacc)
+{
+    const int j = threadIdx.x & 63;
+    const bool pair = j < K - 1;
+    for (int r = wave; r < R; r += nwaves) {
+        const int base = r * K;
+        const int e = Es[base + min(j, K - 1)];
+        // pairs reject a carried energy above b = E_{k+1} + D_k; other lanes never do
+        const int b = pair ? Es[base + j + 1] + xd[r * (K - 1) + j] : INT32_MAX;
+        // run ends: bit k of `ends` set iff slot k keeps the carried configuration
+        uint64_t ends = 0;
+        int x0 = 0;
+        do {
+            const int ec = __builtin_amdgcn_readlane(e, x0);  // the configuration carried from slot x0
+            // lanes with ec > b, straight from the compare (every lane is
+            // active here); the wait states cover ec, just written by a VALU
+            // instruction
+            uint64_t gt;
+            asm volatile("s_nop 1\n\tv_cmp_gt_i32_e64 %0, %1, %2" : "=s"(gt) : "s"(ec), "v"(b));
+            const uint64_t rej = gt & (~0ull << x0);
+            const int st = rej ? int(__builtin_ctzll(rej)) : K - 1;
+            ends |= 1ull << st;
+            x0 = st + 1;
+        } while (x0 < K);
+        if (j < K) {
+            const int en = j + __builtin_ctzll(ends >> j);  // end of j's run
+            const uint64_t below = ends & ((1ull << j) - 1ull);
+            const int xs = below ? 64 - __builtin_clzll(below) : 0;  // start of j's run
+            const int ox = perm[base + xs];
+            const int on = perm[base + min(j + 1, K - 1)];
+            perm[base + j] = j == en ? ox : on;
+            if (pair && j != en) sacc[j * R + r] += 1u;
         }
     }
 }
@@ -809,8 +925,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                 uint32_t *dst = reinterpret_cast<uint32_t *>(tshi);
                 for (int i = tid; i < (tb.lds_ts_entries + 1) / 2; i += blockDim.x) dst[i] = src[i];
             }
-            for (int i = tid; i < R * 64; i += blockDim.x) stopv[i] = K - 1;
-            load_xrows(xrow, tb, a.ws32, K, tid);
+            load_xrows_walk(xrow, tb, a.ws32, K, tid);
             if (tid < 64) {
                 // perm in LDS is set-major (slot r K + k); the buffer holds slot k R + r
                 const int src = tid < K * R ? (tid % K) * R + tid / K : tid;
@@ -867,10 +982,6 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         RoundKeys RK = kPacked ? round_keys_lane(key0, key1) : round_keys(key0, key1);
         RK.a[9] ^= kBias16;
         RK.b[9] ^= kBias16;
-        const int tri = d.tri;
-        const uint32_t tri_m = d.tri_m;
-        // this lane's first test (unpacked; packed launches decode through dec[])
-        const uint32_t xdec = kPacked ? 0u : exchange_test(min(tid, max(tri * R - 1, 0)), tri, tri_m);
 
         // Philox draws do not depend on the exchange passes, since a lane's
         // slot is fixed.  The draws of the first two pairs of phase 0 are made
@@ -879,6 +990,10 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         // pair of the phase, or the first pair of phase 1) is computed while
         // the spin rows of the current pair are being read.
         const int nwalk = min(kPacked ? pk.n_seg : R, nwaves);  // wavefronts of the exchange walk
+        // unpacked launches with at most two walkers: other wavefronts make the
+        // walkers' first draws of the next sweep during the walk
+        const bool hand_ok = !kPacked && (a.lds_mode & kLdsHand) && nwalk <= 2 && nwaves >= 3 * nwalk;
+        uint4 *hand = reinterpret_cast<uint4 *>(lds + L.hand);
         uint4 pre0 = make_uint4(0u, 0u, 0u, 0u), pre1 = pre0;
         auto predraw = [&](const MetroUniform &m) {
             if (nt > 0) pre0 = metro_call(ml, m, task[(wave * 2) * iters * 16], RK);
@@ -1014,8 +1129,15 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         ux[lane] = (live && kslot < K - 1)
                                        ? philox_lane(tt, uint32_t(kslot), uint32_t(set), kUseSwap, key0, key1).x
                                        : 0u;
-                    else
-                        ux[lane] = exchange_uniform(tt, kUseSwap, K, R, key0, key1);
+                    else {
+                        // and the largest energy difference each pair then accepts
+                        const uint32_t u = exchange_uniform(tt, kUseSwap, K, R, key0, key1);
+                        const int km1 = max(K - 1, 1);
+                        const int kp = lane - (lane / km1) * km1;
+                        if (lane < (K - 1) * R)
+                            stopv[lane] = a.lds_ts_ok ? pair_limit<true>(u, kp, xrow, tb, a.ws32, tshi)
+                                                      : pair_limit<false>(u, kp, xrow, tb, a.ws32, tshi);
+                    }
                 }
                 __syncthreads();
             }
@@ -1042,22 +1164,35 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             }
             const bool stop_now = stop_mode && agree && (t + 1) >= 2 * tmax;
             if (cd == 0) {
-                if constexpr (kPacked)
+                if constexpr (kPacked) {
                     exchange_stops_packed(pk.ntest, wave, nwaves, dec, seg_base, Eb, ux, xrow, stopv, a.ws32);
-                else if (a.lds_ts_ok)
-                    exchange_stops<true>(K, R, tri, tri_m, wave, nwaves, xdec, Eb, ux, xrow, stopv, tb, a.ws32,
-                                         tshi);
-                else
-                    exchange_stops<false>(K, R, tri, tri_m, wave, nwaves, xdec, Eb, ux, xrow, stopv, tb, a.ws32,
-                                          tshi);
-                __syncthreads();
-                if (wave >= nwalk) predraw(mu_next);
-                if constexpr (kPacked)
+                    __syncthreads();
+                    if (wave >= nwalk) predraw(mu_next);
                     exchange_apply_packed(pk.n_seg, seg_base, seg_k, wave, nwaves, perm, sacc, stopv);
-                else
-                    exchange_apply(K, R, wave, nwaves, perm, sacc, stopv);
+                } else {
+                    if (wave >= nwalk) {
+                        predraw(mu_next);
+                        // helpers nwalk .. 3 nwalk - 1 also make the walkers' two draws
+                        const int h = wave - nwalk;
+                        if (hand_ok && h < 2 * nwalk) {
+                            const int w = h >> 1, i = h & 1;
+                            const int ntw = w < npairs ? min(iters, (npairs - w + nwaves - 1) / nwaves) : 0;
+                            if (ntw > i)
+                                hand[(w * 2 + i) * 64 + lane] =
+                                    metro_call(ml, mu_next, task[((w * 2) * iters + i) * 16], RK);
+                        }
+                    }
+                    exchange_walk(K, R, wave, nwaves, Eb, stopv, perm, sacc);
+                }
                 __syncthreads();
-                if (wave < nwalk) predraw(mu_next);
+                if (wave < nwalk) {
+                    if (!kPacked && hand_ok) {
+                        if (nt > 0) pre0 = hand[(wave * 2) * 64 + lane];
+                        if (nt > 1) pre1 = hand[(wave * 2 + 1) * 64 + lane];
+                    } else {
+                        predraw(mu_next);
+                    }
+                }
                 col = live ? perm[lane] : lane;
                 if constexpr (kRecord) {
                     // temperature walk: configuration col now sits at temperature kslot
@@ -1548,6 +1683,7 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
         x.ts_hi_off = int64_t(append(img, h.ts_hi.data(), h.ts_hi.size()));
         x.ts_full_off = int64_t(append(img, h.ts_full.data(), h.ts_full.size()));
         x.ts_full_row_off = int64_t(append(img, h.ts_full_row.data(), h.ts_full_row.size()));
+        x.ts_rate_off = int64_t(append(img, h.ts_rate.data(), h.ts_rate.size()));
         P.tshi_max = std::max(P.tshi_max, int(h.ts_hi.size()));
     }
     // Packed launch: the packs, their LDS layout (exchange tables stay in
@@ -1577,7 +1713,8 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
     // LDS layout: the fast exchange table in LDS first, then 4-byte threshold
     // columns, whichever fit
     if (!P.packed) {
-        const int modes[2] = {0, 1};
+        // 4-byte threshold columns first, with the walkers' hand-over if it fits
+        const int modes[4] = {dev::kLdsHand, 0, dev::kLdsHand | 1, 1};
         bool found = false;
         if (size_t(P.tshi_max) * 2 <= kLdsTsBudget) {
             for (int m : modes)
