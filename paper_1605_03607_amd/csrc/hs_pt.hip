@@ -1001,6 +1001,22 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         };
         predraw(metro_uniform(uint32_t(t), kUseMetroHi, key0, key1));
         int64_t n_ex = 0;  // exchange passes made in this launch (recording only)
+        // Unpacked launches: the limits D_k of an exchange pass depend only on
+        // its sweep number, so they are made one pass ahead by the last
+        // wavefront (during the previous pass's walk; the first pass's here),
+        // alternating between two LDS buffers.
+        int32_t *const xlim0 = stopv;
+        int32_t *const xlim1 = reinterpret_cast<int32_t *>(ux);
+        int xb = 0;
+        auto make_limits = [&](uint32_t tp, int32_t *dst) {
+            const uint32_t u = exchange_uniform(tp, kUseSwap, K, R, key0, key1);
+            const int km1 = max(K - 1, 1);
+            const int kp = lane - (lane / km1) * km1;
+            if (lane < (K - 1) * R)
+                dst[lane] = a.lds_ts_ok ? pair_limit<true>(u, kp, xrow, tb, a.ws32, tshi)
+                                        : pair_limit<false>(u, kp, xrow, tb, a.ws32, tshi);
+        };
+        if (!kPacked && si > 0 && wave == nwaves - 1) make_limits(uint32_t(t + cd), xlim0);
 
         for (int64_t sw = 0; sw < a.n_sweeps && !stopped; ++sw) {
             const uint32_t tt = uint32_t(t);
@@ -1123,21 +1139,13 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         __builtin_amdgcn_s_setprio(0);
                 }
                 if (p == 1 && live) atomicAdd(&Eb[lane], (e4 + int(nrej >> 3)) >> 2);
-                // the uniforms of a due exchange pass, drawn by the last wavefront
-                if (p == 1 && cd == 0 && wave == nwaves - 1) {
-                    if constexpr (kPacked)  // by slot: pair (k, k+1) of a set at its lower slot
+                // packed launches: the uniforms of a due exchange pass, drawn by
+                // the last wavefront (by slot: pair (k, k+1) of a set at its lower slot)
+                if constexpr (kPacked) {
+                    if (p == 1 && cd == 0 && wave == nwaves - 1)
                         ux[lane] = (live && kslot < K - 1)
                                        ? philox_lane(tt, uint32_t(kslot), uint32_t(set), kUseSwap, key0, key1).x
                                        : 0u;
-                    else {
-                        // and the largest energy difference each pair then accepts
-                        const uint32_t u = exchange_uniform(tt, kUseSwap, K, R, key0, key1);
-                        const int km1 = max(K - 1, 1);
-                        const int kp = lane - (lane / km1) * km1;
-                        if (lane < (K - 1) * R)
-                            stopv[lane] = a.lds_ts_ok ? pair_limit<true>(u, kp, xrow, tb, a.ws32, tshi)
-                                                      : pair_limit<false>(u, kp, xrow, tb, a.ws32, tshi);
-                    }
                 }
                 __syncthreads();
             }
@@ -1170,6 +1178,8 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     if (wave >= nwalk) predraw(mu_next);
                     exchange_apply_packed(pk.n_seg, seg_base, seg_k, wave, nwaves, perm, sacc, stopv);
                 } else {
+                    // the next pass's limits (by a walker too when every wavefront walks)
+                    if (wave == nwaves - 1) make_limits(tt + uint32_t(si), xb ? xlim0 : xlim1);
                     if (wave >= nwalk) {
                         predraw(mu_next);
                         // helpers nwalk .. 3 nwalk - 1 also make the walkers' two draws
@@ -1182,7 +1192,10 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                                     metro_call(ml, mu_next, task[((w * 2) * iters + i) * 16], RK);
                         }
                     }
-                    exchange_walk(K, R, wave, nwaves, Eb, stopv, perm, sacc);
+                    // the walk is the pass's critical path: its wavefronts issue first
+                    if (wave < nwalk) __builtin_amdgcn_s_setprio(3);
+                    exchange_walk(K, R, wave, nwaves, Eb, xb ? xlim1 : xlim0, perm, sacc);
+                    xb ^= 1;
                 }
                 __syncthreads();
                 if (wave < nwalk) {
