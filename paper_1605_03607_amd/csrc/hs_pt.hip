@@ -465,8 +465,8 @@ __device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm
 // energy E carried into slot k therefore moves on iff E <= B_k = E_{k+1} + D_k,
 // and one wavefront per replica set finds the runs of the ascending pass by a
 // scalar walk: the run from x ends at the first pair k >= x with E_x > B_k.
-// D_k needs no energies, so the wavefront that draws the pass's uniforms
-// computes it before the phase barrier.  It starts from the real bound
+// D_k needs no energies, so one wavefront computes the limits of a pass
+// before the phase barrier that precedes it.  It starts from the real bound
 // (u < 2^32 e^{-db d} iff d < (32 - log2 u) ln 2 / db) and is settled on the
 // integer tables, so every decision equals the test's.
 //
@@ -1001,22 +1001,17 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         };
         predraw(metro_uniform(uint32_t(t), kUseMetroHi, key0, key1));
         int64_t n_ex = 0;  // exchange passes made in this launch (recording only)
-        // Unpacked launches: the limits D_k of an exchange pass depend only on
-        // its sweep number, so they are made one pass ahead by the last
-        // wavefront (during the previous pass's walk; the first pass's here),
-        // alternating between two LDS buffers.
-        int32_t *const xlim0 = stopv;
-        int32_t *const xlim1 = reinterpret_cast<int32_t *>(ux);
-        int xb = 0;
-        auto make_limits = [&](uint32_t tp, int32_t *dst) {
+        // Unpacked launches: the limits D_k of a due exchange pass (they depend
+        // only on the pass's uniforms) into stopv, made at the end of phase 1
+        // by wavefront 0, which walks and leaves its phase-1 tasks early.
+        auto make_limits = [&](uint32_t tp) {
             const uint32_t u = exchange_uniform(tp, kUseSwap, K, R, key0, key1);
             const int km1 = max(K - 1, 1);
             const int kp = lane - (lane / km1) * km1;
             if (lane < (K - 1) * R)
-                dst[lane] = a.lds_ts_ok ? pair_limit<true>(u, kp, xrow, tb, a.ws32, tshi)
-                                        : pair_limit<false>(u, kp, xrow, tb, a.ws32, tshi);
+                stopv[lane] = a.lds_ts_ok ? pair_limit<true>(u, kp, xrow, tb, a.ws32, tshi)
+                                          : pair_limit<false>(u, kp, xrow, tb, a.ws32, tshi);
         };
-        if (!kPacked && si > 0 && wave == nwaves - 1) make_limits(uint32_t(t + cd), xlim0);
 
         for (int64_t sw = 0; sw < a.n_sweeps && !stopped; ++sw) {
             const uint32_t tt = uint32_t(t);
@@ -1139,13 +1134,16 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                         __builtin_amdgcn_s_setprio(0);
                 }
                 if (p == 1 && live) atomicAdd(&Eb[lane], (e4 + int(nrej >> 3)) >> 2);
-                // packed launches: the uniforms of a due exchange pass, drawn by
-                // the last wavefront (by slot: pair (k, k+1) of a set at its lower slot)
+                // the uniforms of a due exchange pass (packed launches: drawn by the
+                // last wavefront, by slot: pair (k, k+1) of a set at its lower
+                // slot), or its limits
                 if constexpr (kPacked) {
                     if (p == 1 && cd == 0 && wave == nwaves - 1)
                         ux[lane] = (live && kslot < K - 1)
                                        ? philox_lane(tt, uint32_t(kslot), uint32_t(set), kUseSwap, key0, key1).x
                                        : 0u;
+                } else {
+                    if (p == 1 && cd == 0 && wave == 0) make_limits(tt);
                 }
                 __syncthreads();
             }
@@ -1178,8 +1176,6 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     if (wave >= nwalk) predraw(mu_next);
                     exchange_apply_packed(pk.n_seg, seg_base, seg_k, wave, nwaves, perm, sacc, stopv);
                 } else {
-                    // the next pass's limits (by a walker too when every wavefront walks)
-                    if (wave == nwaves - 1) make_limits(tt + uint32_t(si), xb ? xlim0 : xlim1);
                     if (wave >= nwalk) {
                         predraw(mu_next);
                         // helpers nwalk .. 3 nwalk - 1 also make the walkers' two draws
@@ -1194,8 +1190,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                     }
                     // the walk is the pass's critical path: its wavefronts issue first
                     if (wave < nwalk) __builtin_amdgcn_s_setprio(3);
-                    exchange_walk(K, R, wave, nwaves, Eb, xb ? xlim1 : xlim0, perm, sacc);
-                    xb ^= 1;
+                    exchange_walk(K, R, wave, nwaves, Eb, stopv, perm, sacc);
                 }
                 __syncthreads();
                 if (wave < nwalk) {
