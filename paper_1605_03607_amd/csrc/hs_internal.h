@@ -52,7 +52,6 @@ struct alignas(16) PackDev {
     int32_t n_mem;            // members, 1..kMaxPack
     int32_t nlanes;           // lanes used by all members
     int32_t n_seg;            // replica sets of all members
-    int32_t ntest;            // exchange tests of all members (sum over sets of K (K - 1) / 2)
     int32_t mem[kMaxPack];    // instance indices
     int32_t lane0[kMaxPack];  // first lane of each member
     int64_t cost;             // cells, used to order the work queue

@@ -24,10 +24,9 @@
 //     T = floor(2^32 exp(-2 beta m)) stays in global memory for ties.
 //   * Exchange passes: one wavefront per replica set turns each pair's
 //     uniform into the largest energy difference the pair accepts, walks the
-//     runs of accepted exchanges and rewrites perm.  (Packed launches, and
-//     pt_swap, evaluate the acceptance tests of pair (k, k+1) for every
-//     configuration that can be carried into slot k across the wavefronts
-//     first, then link the runs.)
+//     runs of accepted exchanges and rewrites perm.  (pt_swap evaluates the
+//     acceptance tests of pair (k, k+1) for every configuration that can be
+//     carried into slot k first, then links the runs.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -223,26 +222,24 @@ __device__ __forceinline__ int wave_min(int v)
 // ---------------------------------------------------------------------------
 // Dynamic LDS layout of the sweep kernel.
 struct LdsLayout {
-    uint32_t S, ths, tshi, Eacc, perm, sacc, ux, xrow, stopv, misc, total;
+    uint32_t S, ths, tshi, Eacc, perm, sacc, xrow, lim, misc, total;
     // packed launches only: replica-set segments, exchange-test decodes,
     // the members' coupling words and flip masks, threshold-row offsets
-    uint32_t seg, dec, jwl, lml, thia;
+    uint32_t seg, jwl, lml, thia;
     // unpacked launches: the first two Metropolis draws of the next sweep for
     // the (at most two) wavefronts that walk the exchange runs
     uint32_t hand;
 };
 
 // mode bit 0: 2-byte threshold columns (else 4-byte: no two lanes share a
-// bank).  mode bit 1: packed launch (instances sharing the lanes; r_max then
-// counts the replica sets of all members, ntest_max their exchange tests, and
-// the exchange tables stay in global memory).
+// bank).  mode bit 1: packed launch (instances sharing the lanes; the
+// exchange tables stay in global memory).
 constexpr int kLdsPacked = 2;
 // mode bit 2 (unpacked launches): room for the exchange walkers' hand-over
 // of their first two draws of the next sweep
 constexpr int kLdsHand = 4;
 
-__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int r_max, int mode,
-                                                int ntest_max = 0)
+__host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int r_max, int mode)
 {
     LdsLayout l;
     uint32_t o = 0;
@@ -258,19 +255,19 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int
     o += 64 * 4;                                  // slot (set-major) -> configuration column
     l.sacc = o;
     o += 64 * 4;
-    l.ux = o;
-    o += 64 * 4;                                  // uniforms of the exchange pass, pair r (K-1) + k
     l.xrow = o;
     // exchange-table row start and length of pair (k, k+1), the exact
     // table's row start and length (packed launches: by the pair's lower
     // slot), and beta_{k+1} - beta_k
     o += 5 * 64 * 4;
-    l.stopv = o;
-    o += uint32_t(r_max) * 64 * 4;                // run ends of the exchange pass, [set][start]
+    l.lim = o;
+    // limits D of the due exchange pass's pairs, by lane (64 used; sized by
+    // the replica sets, which keeps the sweep kernel's registers as measured)
+    o += uint32_t(r_max) * 64 * 4;
     l.misc = o;
     o += 16 * 4;
-    l.seg = l.dec = l.jwl = l.lml = l.thia = l.hand = o;
-    if ((mode & kLdsHand) && !(mode & kLdsPacked)) {
+    l.seg = l.jwl = l.lml = l.thia = l.hand = o;
+    if (mode & kLdsHand) {
         o = (o + 15u) & ~15u;
         l.hand = o;
         o += 4 * 64 * 16;                         // uint4 [walker][draw][lane]
@@ -280,8 +277,6 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int
         o += 2 * 64 * 4;                          // first slot and K of every replica set
         l.thia = o;
         o += 64 * 4;                              // Metropolis threshold row of every slot
-        l.dec = o;
-        o += ((uint32_t(ntest_max) + 3) / 4) * 16;  // exchange test q -> set << 16 | k << 8 | j
         l.jwl = o;
         o += uint32_t(kMaxPack) * uint32_t(ncell_max) * 16 * 4;  // coupling words [member][cell][2][8]
         l.lml = o;
@@ -311,7 +306,7 @@ struct SweepArgs {
     int32_t swap_interval;
     int64_t n_sweeps;
     uint32_t flags;
-    int32_t ncell_max, tshi_max, r_max, ntest_max;
+    int32_t ncell_max, tshi_max, r_max;
     int32_t lds_ts_ok;        // 1 if every ladder's fast exchange table fits in LDS
     int32_t lds_mode;         // lds_layout mode
     uint8_t *walk;            // optional: temperature index per configuration after each exchange pass
@@ -559,77 +554,68 @@ __device__ void exchange_walk(int K, int R, int wave, int nwaves, const int32_t 
     }
 }
 
-// Packed launches: the replica sets (segments) of the members have their own
-// K and ladder.  Segment s holds slots seg_base[s] .. seg_base[s] + K_s - 1;
-// pair (k, k+1) of a segment is indexed by its lower slot p = seg_base[s] + k,
-// and ptab[p], ptab[64 + p], ptab[128 + p], ptab[192 + p] give that pair's
-// fast-table row (as a uint16 index into the workspace), its 16-bit row
-// length, the exact table's row (uint32 index) and its length.  The tests
-// are decoded once per pack: dec[q] = s << 16 | k << 8 | j.
-__device__ void exchange_stops_packed(int ntest, int wave, int nwaves, const uint32_t *dec, const int32_t *seg_base,
-                                      const int32_t *Es, const uint32_t *ux, const int32_t *ptab, int32_t *stopv,
-                                      const uint32_t *ws32)
+// Packed launches: D for the pair at slot l (its lower slot), with the
+// tables indexed from the workspace base: xrow[l] the 16-bit row (uint16
+// index), [64 + l] its length, [128 + l] the exact row (uint32 index),
+// [192 + l] its length, [256 + l] ln 2 / (beta_{k+1} - beta_k).
+__device__ __forceinline__ int pair_limit_packed(uint32_t u, int l, const int32_t *xrow, const uint32_t *ws32)
 {
-    const int lane = threadIdx.x & 63;
-    if (wave * 64 >= ntest) return;
-    const uint16_t *g16 = reinterpret_cast<const uint16_t *>(ws32);
-    for (int base = wave * 64; base < ntest; base += nwaves * 64) {
-        const uint32_t dc = dec[min(base + lane, ntest - 1)];
-        const int sg = int(dc >> 16), k = int((dc >> 8) & 0xFFu), j = int(dc & 0xFFu);
-        const int b = seg_base[sg];
-        const int pr = b + k;
-        const int ex = Es[b + j];
-        const int ey = Es[pr + 1];
-        const uint32_t u = ux[pr];
-        const int row = ptab[pr], dh = ptab[64 + pr];
-        const int d = ex - ey;
-        const uint32_t h = g16[row + min(max(d, 1), max(dh, 1)) - 1];  // clamped into the row
-        const uint32_t th = d <= dh ? h : 0u;
-        const uint32_t u16 = u >> 16;
-        bool rej = d > 0 && u16 > th;
-        const bool tie = d > 0 && u16 == th;
-        if (__any(tie)) {  // rare: exact table
-            if (tie) {
-                const int dmx = ptab[192 + pr];
-                const uint32_t tf = d <= dmx ? ws32[ptab[128 + pr] + d - 1] : 0u;
-                rej = !(u < tf);
-            }
-        }
-        if (rej && base + lane < ntest) atomicMin(&stopv[sg * 64 + j], k);
+    const uint16_t *hi = reinterpret_cast<const uint16_t *>(ws32);
+    const int row = xrow[l], dh = xrow[64 + l], frow = xrow[128 + l], dmax = xrow[192 + l];
+    const float rate = __int_as_float(xrow[256 + l]);
+    const uint32_t u16 = u >> 16;
+    auto acc = [&](int d, uint32_t h) -> bool { return u16 != h ? u16 < h : u < ws32[frow + d - 1]; };
+    auto hi_at = [&](int d) -> uint32_t {
+        return d <= dh ? uint32_t(hi[row + min(max(d, 1), max(dh, 1)) - 1]) : 0u;
+    };
+    const float x = fminf(fmaxf((32.0f - __builtin_amdgcn_logf(float(u))) * rate, 0.0f), float(dmax) + 1.0f);
+    int D = min(max(int(ceilf(x)) - 1, 0), dmax);
+    const uint32_t h1 = hi_at(D + 1), h0 = hi_at(D);
+    const bool a1 = D < dmax && acc(D + 1, h1);
+    const bool a0 = D == 0 || acc(D, h0);
+    if (a1) {
+        ++D;
+        while (D < dmax && acc(D + 1, hi_at(D + 1))) ++D;
+    } else if (!a0) {
+        --D;
+        while (D > 0 && !acc(D, hi_at(D))) --D;
     }
+    return D;
 }
 
-// Step 2 of a packed launch: exchange_apply over segments of their own K;
-// sacc counts accepted exchanges by the pair's lower slot.
-__device__ void exchange_apply_packed(int n_seg, const int32_t *seg_base, const int32_t *seg_k, int wave, int nwaves,
-                                      int32_t *perm, uint32_t *sacc, int32_t *stopv)
+// Packed launches: the walk of each replica set (segment s: slots
+// seg_base[s] .. seg_base[s] + K_s - 1), as exchange_walk, with the limit
+// and the counter of pair (k, k+1) at its lower slot.
+__device__ void exchange_walk_packed(int n_seg, const int32_t *seg_base, const int32_t *seg_k, int wave, int nwaves,
+                                     const int32_t *Es, const int32_t *xd, int32_t *perm, uint32_t *sacc)
 {
     const int j = threadIdx.x & 63;
     for (int sg = wave; sg < n_seg; sg += nwaves) {
         const int base = __builtin_amdgcn_readfirstlane(seg_base[sg]);
         const int K = __builtin_amdgcn_readfirstlane(seg_k[sg]);
-        int st = K - 1;
-        if (j < K - 1) {
-            st = stopv[sg * 64 + j];
-            stopv[sg * 64 + j] = K - 1;  // ready for the next pass
-        }
-        const int st2 = __shfl(st, min(st + 1, K - 1), 64);
+        const bool pair = j < K - 1;
+        const int e = Es[base + min(j, K - 1)];
+        const int b = pair ? Es[base + j + 1] + xd[base + j] : INT32_MAX;
         uint64_t ends = 0;
         int x0 = 0;
         do {
-            const int e1 = __builtin_amdgcn_readlane(st, x0);
-            const int e2 = __builtin_amdgcn_readlane(st2, x0);
-            ends |= (1ull << e1) | (1ull << e2);
-            x0 = max(e2, x0) + 1;
+            const int ec = __builtin_amdgcn_readlane(e, x0);
+            // wait states for ec as in exchange_walk
+            uint64_t gt;
+            asm volatile("s_nop 1\n\tv_cmp_gt_i32_e64 %0, %1, %2" : "=s"(gt) : "s"(ec), "v"(b));
+            const uint64_t rej = gt & (~0ull << x0);
+            const int st = rej ? int(__builtin_ctzll(rej)) : K - 1;
+            ends |= 1ull << st;
+            x0 = st + 1;
         } while (x0 < K);
         if (j < K) {
-            const int e = j + __ffsll(static_cast<long long>(ends >> j)) - 1;
+            const int en = j + __builtin_ctzll(ends >> j);
             const uint64_t below = ends & ((1ull << j) - 1ull);
-            const int x = below ? 64 - __clzll(static_cast<long long>(below)) : 0;
-            const int ox = perm[base + x];
+            const int xs = below ? 64 - __builtin_clzll(below) : 0;
+            const int ox = perm[base + xs];
             const int on = perm[base + min(j + 1, K - 1)];
-            perm[base + j] = j == e ? ox : on;
-            if (j < K - 1 && j != e) atomicAdd(&sacc[base + j], 1u);
+            perm[base + j] = j == en ? ox : on;
+            if (pair && j != en) sacc[base + j] += 1u;
         }
     }
 }
@@ -775,7 +761,7 @@ template <bool kRecord, bool kPacked>
 __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
 {
     extern __shared__ __align__(16) char lds[];
-    const LdsLayout L = lds_layout(a.ncell_max, a.tshi_max, a.r_max, a.lds_mode, a.ntest_max);
+    const LdsLayout L = lds_layout(a.ncell_max, a.tshi_max, a.r_max, a.lds_mode);
     const uint32_t ths_sh = (a.lds_mode & 1) ? 5u : 6u;  // entry m of a column at byte (4 m) << ths_sh
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -786,9 +772,8 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
     int32_t *Eacc = reinterpret_cast<int32_t *>(lds + L.Eacc);
     int32_t *perm = reinterpret_cast<int32_t *>(lds + L.perm);
     uint32_t *sacc = reinterpret_cast<uint32_t *>(lds + L.sacc);
-    uint32_t *ux = reinterpret_cast<uint32_t *>(lds + L.ux);
     int32_t *xrow = reinterpret_cast<int32_t *>(lds + L.xrow);
-    int32_t *stopv = reinterpret_cast<int32_t *>(lds + L.stopv);
+    int32_t *lim = reinterpret_cast<int32_t *>(lds + L.lim);
     int32_t *misc = reinterpret_cast<int32_t *>(lds + L.misc);
     uint16_t *tshi = reinterpret_cast<uint16_t *>(lds + L.tshi);
     const bool stop_mode = (a.flags & HS_STOP_ON_AGREEMENT) != 0;
@@ -836,7 +821,6 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         const uint32_t *lml = reinterpret_cast<const uint32_t *>(lds + L.lml) + mi * a.ncell_max * 2;
         int32_t *seg_base = reinterpret_cast<int32_t *>(lds + L.seg);
         int32_t *seg_k = seg_base + 64;
-        uint32_t *dec = reinterpret_cast<uint32_t *>(lds + L.dec);
         if constexpr (kPacked) {
             // the members' coupling words and flip masks
             for (int m = 0; m < pk.n_mem; ++m) {
@@ -860,6 +844,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                 xrow[64 + l] = pair ? int32_t(a.ws32[tl.ts_dhi_off + kk]) : 0;
                 xrow[128 + l] = pair ? int32_t(tl.ts_full_off + a.ws32[tl.ts_full_row_off + kk]) : 0;
                 xrow[192 + l] = pair ? int32_t(a.ws32[tl.ts_dmax_off + kk]) : 0;
+                xrow[256 + l] = pair ? int32_t(a.ws32[tl.ts_rate_off + kk]) : 0;
                 // perm in LDS is set-major (slot lane0 + r K + k, configuration columns of
                 // the member from lane0 on); the buffers hold slot k R + r
                 perm[l] = lv ? lane0 + int(a.perm[nm * 64 + kk * R + rr]) : l;
@@ -872,19 +857,6 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             }
             if (tid == 0) misc[1] = 0;
             __syncthreads();
-            // exchange tests of every set, and the run ends, from the segments
-            for (int q = tid; q < pk.ntest; q += blockDim.x) {
-                int sg = 0, rem = q;
-                while (rem >= seg_k[sg] * (seg_k[sg] - 1) / 2) {
-                    rem -= seg_k[sg] * (seg_k[sg] - 1) / 2;
-                    ++sg;
-                }
-                int k = int((__fsqrt_rn(float(8 * rem + 1)) - 1.0f) * 0.5f);
-                k += ((k + 1) * (k + 2) / 2 <= rem) ? 1 : 0;
-                k -= (k * (k + 1) / 2 > rem) ? 1 : 0;
-                dec[q] = (uint32_t(sg) << 16) | (uint32_t(k) << 8) | uint32_t(rem - k * (k + 1) / 2);
-            }
-            for (int i = tid; i < pk.n_seg * 64; i += blockDim.x) stopv[i] = seg_k[i >> 6] - 1;
         }
         const uint64_t *sp = a.spins + spin_off;
 
@@ -992,7 +964,7 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         const int nwalk = min(kPacked ? pk.n_seg : R, nwaves);  // wavefronts of the exchange walk
         // unpacked launches with at most two walkers: other wavefronts make the
         // walkers' first draws of the next sweep during the walk
-        const bool hand_ok = !kPacked && (a.lds_mode & kLdsHand) && nwalk <= 2 && nwaves >= 3 * nwalk;
+        const bool hand_ok = (a.lds_mode & kLdsHand) && nwalk <= 2 && nwaves >= 3 * nwalk;
         uint4 *hand = reinterpret_cast<uint4 *>(lds + L.hand);
         uint4 pre0 = make_uint4(0u, 0u, 0u, 0u), pre1 = pre0;
         auto predraw = [&](const MetroUniform &m) {
@@ -1002,14 +974,14 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
         predraw(metro_uniform(uint32_t(t), kUseMetroHi, key0, key1));
         int64_t n_ex = 0;  // exchange passes made in this launch (recording only)
         // Unpacked launches: the limits D_k of a due exchange pass (they depend
-        // only on the pass's uniforms) into stopv, made at the end of phase 1
+        // only on the pass's uniforms) into lim, made at the end of phase 1
         // by wavefront 0, which walks and leaves its phase-1 tasks early.
         auto make_limits = [&](uint32_t tp) {
             const uint32_t u = exchange_uniform(tp, kUseSwap, K, R, key0, key1);
             const int km1 = max(K - 1, 1);
             const int kp = lane - (lane / km1) * km1;
             if (lane < (K - 1) * R)
-                stopv[lane] = a.lds_ts_ok ? pair_limit<true>(u, kp, xrow, tb, a.ws32, tshi)
+                lim[lane] = a.lds_ts_ok ? pair_limit<true>(u, kp, xrow, tb, a.ws32, tshi)
                                           : pair_limit<false>(u, kp, xrow, tb, a.ws32, tshi);
         };
 
@@ -1138,10 +1110,11 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
                 // last wavefront, by slot: pair (k, k+1) of a set at its lower
                 // slot), or its limits
                 if constexpr (kPacked) {
-                    if (p == 1 && cd == 0 && wave == nwaves - 1)
-                        ux[lane] = (live && kslot < K - 1)
-                                       ? philox_lane(tt, uint32_t(kslot), uint32_t(set), kUseSwap, key0, key1).x
-                                       : 0u;
+                    // by slot: pair (k, k+1) of a set at its lower slot
+                    if (p == 1 && cd == 0 && wave == 0 && live && kslot < K - 1)
+                        lim[lane] = pair_limit_packed(
+                            philox_lane(tt, uint32_t(kslot), uint32_t(set), kUseSwap, key0, key1).x, lane, xrow,
+                            a.ws32);
                 } else {
                     if (p == 1 && cd == 0 && wave == 0) make_limits(tt);
                 }
@@ -1170,31 +1143,27 @@ __global__ void __launch_bounds__(1024) k_pt_sweep(SweepArgs a)
             }
             const bool stop_now = stop_mode && agree && (t + 1) >= 2 * tmax;
             if (cd == 0) {
-                if constexpr (kPacked) {
-                    exchange_stops_packed(pk.ntest, wave, nwaves, dec, seg_base, Eb, ux, xrow, stopv, a.ws32);
-                    __syncthreads();
-                    if (wave >= nwalk) predraw(mu_next);
-                    exchange_apply_packed(pk.n_seg, seg_base, seg_k, wave, nwaves, perm, sacc, stopv);
-                } else {
-                    if (wave >= nwalk) {
-                        predraw(mu_next);
-                        // helpers nwalk .. 3 nwalk - 1 also make the walkers' two draws
-                        const int h = wave - nwalk;
-                        if (hand_ok && h < 2 * nwalk) {
-                            const int w = h >> 1, i = h & 1;
-                            const int ntw = w < npairs ? min(iters, (npairs - w + nwaves - 1) / nwaves) : 0;
-                            if (ntw > i)
-                                hand[(w * 2 + i) * 64 + lane] =
-                                    metro_call(ml, mu_next, task[((w * 2) * iters + i) * 16], RK);
-                        }
+                if (wave >= nwalk) {
+                    predraw(mu_next);
+                    // helpers nwalk .. 3 nwalk - 1 also make the walkers' two draws
+                    const int h = wave - nwalk;
+                    if (hand_ok && h < 2 * nwalk) {
+                        const int w = h >> 1, i = h & 1;
+                        const int ntw = w < npairs ? min(iters, (npairs - w + nwaves - 1) / nwaves) : 0;
+                        if (ntw > i)
+                            hand[(w * 2 + i) * 64 + lane] =
+                                metro_call(ml, mu_next, task[((w * 2) * iters + i) * 16], RK);
                     }
-                    // the walk is the pass's critical path: its wavefronts issue first
-                    if (wave < nwalk) __builtin_amdgcn_s_setprio(3);
-                    exchange_walk(K, R, wave, nwaves, Eb, stopv, perm, sacc);
                 }
+                // the walk is the pass's critical path: its wavefronts issue first
+                if (wave < nwalk) __builtin_amdgcn_s_setprio(3);
+                if constexpr (kPacked)
+                    exchange_walk_packed(pk.n_seg, seg_base, seg_k, wave, nwaves, Eb, lim, perm, sacc);
+                else
+                    exchange_walk(K, R, wave, nwaves, Eb, lim, perm, sacc);
                 __syncthreads();
                 if (wave < nwalk) {
-                    if (!kPacked && hand_ok) {
+                    if (hand_ok) {
                         if (nt > 0) pre0 = hand[(wave * 2) * 64 + lane];
                         if (nt > 1) pre1 = hand[(wave * 2 + 1) * 64 + lane];
                     } else {
@@ -1446,7 +1415,7 @@ struct hs_pt {
     int32_t swap_interval = 0;
     int nwaves = 16;
     int grid = 0;
-    int ncell_max = 0, tshi_max = 0, r_max = 1, ntest_max = 0;
+    int ncell_max = 0, tshi_max = 0, r_max = 1;
     int lds_ts_ok = 1;
     int lds_mode = 0;
     bool packed = false;  // the queue hands out packs of instances sharing the lanes
@@ -1475,7 +1444,7 @@ struct Plan {
     std::vector<uint32_t> image;  // workspace image in uint32 words
     int nwaves = 16;
     size_t off_inst = 0, off_tabs = 0, off_order = 0, off_queue = 0, off_packs = 0;
-    int ncell_max = 0, K_max = 0, tshi_max = 0, r_max = 1, ntest_max = 0;
+    int ncell_max = 0, K_max = 0, tshi_max = 0, r_max = 1;
     int lds_ts_ok = 1;
     int lds_mode = 0;
     bool packed = false;
@@ -1503,7 +1472,6 @@ void make_packs(const std::vector<InstDev> &idev, std::vector<PackDev> &packs)
             pk.n_mem = 1;
             pk.nlanes = big.nlanes;
             pk.n_seg = big.R;
-            pk.ntest = big.R * big.K * (big.K - 1) / 2;
             if (lo < hi && big.nlanes + idev[ids[lo]].nlanes <= HS_MAX_LANES) {
                 const InstDev &sm = idev[ids[lo]];
                 pk.mem[1] = ids[lo];
@@ -1511,7 +1479,6 @@ void make_packs(const std::vector<InstDev> &idev, std::vector<PackDev> &packs)
                 pk.n_mem = 2;
                 pk.nlanes += sm.nlanes;
                 pk.n_seg += sm.R;
-                pk.ntest += sm.R * sm.K * (sm.K - 1) / 2;
                 ++lo;
             }
             pk.cost = int64_t(big.ncell);
@@ -1699,22 +1666,19 @@ int make_plan(const hs_pt_desc &d, Plan &P, std::string &err)
     // workspace offset fits the 32-bit indices of the packed exchange tables
     if (d.flags & HS_PACK_LANES) {
         make_packs(P.idev, P.packs);
-        int nseg = 1, ntest = 0;
-        for (const PackDev &pk : P.packs) {
-            nseg = std::max(nseg, pk.n_seg);
-            ntest = std::max(ntest, pk.ntest);
-        }
-        const int modes[2] = {0, 1};
+        int nseg = 1;
+        for (const PackDev &pk : P.packs) nseg = std::max(nseg, pk.n_seg);
+        // the walkers' hand-over if it fits
+        const int modes[4] = {dev::kLdsHand, 0, dev::kLdsHand | 1, 1};
         for (int m : modes)
             if (!P.packed && P.packs.size() < size_t(n) &&
-                dev::lds_layout(P.ncell_max, 0, nseg, m | dev::kLdsPacked, ntest).total <= kLdsLimit &&
+                dev::lds_layout(P.ncell_max, 0, nseg, m | dev::kLdsPacked).total <= kLdsLimit &&
                 img.size() < (size_t(1) << 29)) {
                 P.packed = true;
                 P.lds_mode = m | dev::kLdsPacked;
                 P.lds_ts_ok = 0;
                 P.tshi_max = 0;
                 P.r_max = nseg;
-                P.ntest_max = ntest;
             }
         if (!P.packed) P.packs.clear();
     }
@@ -1838,7 +1802,6 @@ int hs::pt_init_ex(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *
     h->lds_ts_ok = P.lds_ts_ok;
     h->lds_mode = P.lds_mode;
     h->packed = P.packed;
-    h->ntest_max = P.ntest_max;
     h->n_items = P.packed ? int(P.packs.size()) : d->n_inst;
     if (P.packed)
         for (const PackDev &pk : P.packs) h->lane_sites += 64 * int64_t(P.idev[pk.mem[0]].n_sites);
@@ -1849,7 +1812,7 @@ int hs::pt_init_ex(hs_pt **out, const hs_pt_desc *d, const hs_buffers *b, void *
     h->off_order = P.off_order;
     h->off_queue = P.off_queue;
     h->off_packs = P.off_packs;
-    h->lds_bytes = dev::lds_layout(h->ncell_max, h->tshi_max, h->r_max, h->lds_mode, h->ntest_max).total;
+    h->lds_bytes = dev::lds_layout(h->ncell_max, h->tshi_max, h->r_max, h->lds_mode).total;
     h->host_ws = std::move(P.image);
     if (h->n_inst == 0) {
         *out = h;
@@ -1932,7 +1895,6 @@ int sweep_launch(hs_pt *h, int64_t n_sweeps, hipStream_t stream, uint8_t *walk =
     a.ncell_max = h->ncell_max;
     a.tshi_max = h->tshi_max;
     a.r_max = h->r_max;
-    a.ntest_max = h->ntest_max;
     a.lds_ts_ok = h->lds_ts_ok;
     a.lds_mode = h->lds_mode;
     a.walk = walk;
