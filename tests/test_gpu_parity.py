@@ -116,6 +116,29 @@ def test_launch_shape_does_not_change_results(waves):
     b.close()
 
 
+@pytest.mark.parametrize("waves,K,R", [(3, 48, 1), (5, 32, 2), (6, 32, 2), (7, 32, 2), (12, 20, 3), (16, 1, 7)])
+def test_exchange_walkers_and_hand_over_shapes(waves, K, R):
+    """Launch shapes at the edges of the exchange pass's work split: one
+    walking wavefront per replica set, and other wavefronts handing over the
+    walkers' next draws only when there are at least three wavefronts per
+    walker (on with 3 for one set and 6 or 7 for two, off with 5, and never
+    with three sets); one-temperature sets have no pairs.  An exchange pass
+    after every sweep; bit-exact against the oracle."""
+    hs = _gpu()
+    insts = []
+    for n, L in enumerate((4, 5, 3)):
+        insts.append(dict(L=L, J=workloads.couplings(L, "pm7", 77, n), live=workloads.missing_mask(L, 0.02, 77, n),
+                          K=K, R=R, beta=workloads.geometric_betas(0.1, 5.0, K), instance_id=4200 + n))
+    b = hs.PTBatch(insts, SEED, swap_interval=1, block_waves=waves)
+    assert b.launch_shape()[1] == waves
+    _say(f"walker shapes: {waves} wavefronts, K={K} R={R}")
+    b.sweep(60)
+    assert b.measure() == 0
+    for n, d in enumerate(insts):
+        _assert_same(b.state(n), _oracle_run(d, SEED, 1, 60), f"waves={waves} K={K} R={R} instance {n}")
+    b.close()
+
+
 def test_init_from_buffer_and_gauge_images():
     """Caller-provided initial spins; and the gauge transform (J', s0') =
     (gJg, g.s0) gives s'(t) = g.s(t) with identical energies and perms."""
