@@ -223,11 +223,11 @@ __device__ __forceinline__ int wave_min(int v)
 // Dynamic LDS layout of the sweep kernel.
 struct LdsLayout {
     uint32_t S, ths, tshi, Eacc, perm, sacc, xrow, lim, misc, total;
-    // packed launches only: replica-set segments, exchange-test decodes,
-    // the members' coupling words and flip masks, threshold-row offsets
+    // packed launches only: replica-set segments, the members' coupling
+    // words and flip masks, threshold-row offsets
     uint32_t seg, jwl, lml, thia;
-    // unpacked launches: the first two Metropolis draws of the next sweep for
-    // the (at most two) wavefronts that walk the exchange runs
+    // the first two Metropolis draws of the next sweep for the (at most two)
+    // wavefronts that walk the exchange runs
     uint32_t hand;
 };
 
@@ -235,8 +235,8 @@ struct LdsLayout {
 // bank).  mode bit 1: packed launch (instances sharing the lanes; the
 // exchange tables stay in global memory).
 constexpr int kLdsPacked = 2;
-// mode bit 2 (unpacked launches): room for the exchange walkers' hand-over
-// of their first two draws of the next sweep
+// mode bit 2: room for the exchange walkers' hand-over of their first two
+// draws of the next sweep
 constexpr int kLdsHand = 4;
 
 __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int r_max, int mode)
@@ -258,7 +258,7 @@ __host__ __device__ inline LdsLayout lds_layout(int ncell_max, int tshi_max, int
     l.xrow = o;
     // exchange-table row start and length of pair (k, k+1), the exact
     // table's row start and length (packed launches: by the pair's lower
-    // slot), and beta_{k+1} - beta_k
+    // slot), and ln 2 / (beta_{k+1} - beta_k)
     o += 5 * 64 * 4;
     l.lim = o;
     // limits D of the due exchange pass's pairs, by lane (64 used; sized by
