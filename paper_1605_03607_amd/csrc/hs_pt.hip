@@ -452,7 +452,8 @@ __device__ void exchange_apply(int K, int R, int wave, int nwaves, int32_t *perm
     }
 }
 
-// The exchange pass by critical energy differences (unpacked launches).  For
+// The exchange pass by critical energy differences (packed launches use the
+// same, through pair_limit_packed and exchange_walk_packed below).  For
 // pair (k, k+1) with uniform u the test "d <= 0 or u < T_k(d)" accepts a set
 // of differences closed downwards, since T_k(d) = floor(2^32 e^{-(beta_{k+1} -
 // beta_k) d}) does not grow with d (0 beyond the table): it accepts exactly
